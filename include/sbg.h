@@ -1,0 +1,144 @@
+/*
+ * sbg.h -- batched GEMM over many small matrices on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Jhurani & Mullowney, "A GEMM interface and implementation on
+ * NVIDIA GPUs for multiple small matrices", Sec. 2, Eq. (1)):
+ *
+ *     C_p <- alpha * op(A_p) * op(B_p) + beta * C_p,      p = 0 .. batch_count-1,
+ *
+ * with C_p m x n, op(A_p) m x k, op(B_p) k x n, and 0 <= m, n, k <= 16.
+ * op(X) is selected per operand by a character (Sec. 2; Sec. 5 argument list):
+ *     'N'/'n'  X            'T'/'t'  X^T            'C'/'c'  X^H (conjugate transpose)
+ *     'R'/'r'  conj(X), no transpose -- an extension not in the paper, used to
+ *              express gradients of complex products as one more call.
+ * For real types 'C' equals 'T' and 'R' equals 'N'.
+ *
+ * Storage: every matrix is column-major; leading dimensions and strides are in
+ * ELEMENTS, never bytes (Sec. 5).  Element (i, j) of the p-th matrix of a
+ * strided batch is X[i + ld * j + stride * p] (the paper's second leading
+ * dimension, here 64-bit).
+ *
+ * Scalar types (suffix letter as in BLAS): s = float, d = double,
+ * c = sbg_cfloat, z = sbg_cdouble (interleaved real, imaginary parts).
+ *
+ * Ownership and execution: all matrix, pointer-array and dimension memory is
+ * DEVICE memory owned by the caller.  Calls are asynchronous on `stream` (a
+ * hipStream_t; NULL = the legacy default stream) and never allocate, copy to
+ * the host or synchronise.  alpha and beta are read at call time from HOST
+ * memory (default) or, after sbg_set_scalar_mode(SBG_SCALAR_DEVICE), at kernel
+ * time from DEVICE memory.  Invalid device pointers are undefined behaviour, as
+ * in BLAS.  Calls on one stream are ordered; calls writing overlapping C on
+ * different streams race.
+ *
+ * Errors: SBG_INVALID_VALUE with the 1-based position of the first rejected
+ * argument recorded for sbg_last_invalid_arg() (checked in argument order, as
+ * BLAS's xerbla does); SBG_NOT_SUPPORTED for m, n or k above 16;
+ * SBG_HIP_ERROR when the kernel launch fails.  Nothing is launched unless the
+ * result is SBG_OK.
+ *
+ * Quick returns (no launch, SBG_OK): m == 0, n == 0, batch_count == 0, or
+ * (alpha == 0 or k == 0) and beta == 1 (host scalar mode only).
+ * Special cases of the definition (Sec. 6, the a1b0 and axpby functors):
+ * when alpha == 0 neither A nor B is read; when beta == 0 C is not read, so
+ * NaN or Inf there never reaches the result.
+ */
+#ifndef SBG_H
+#define SBG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SBG_OK = 0,
+    SBG_INVALID_VALUE = 1,
+    SBG_NOT_SUPPORTED = 2,
+    SBG_HIP_ERROR = 3,
+    SBG_WORKSPACE_TOO_SMALL = 4
+} sbg_status_t;
+
+typedef enum { SBG_SCALAR_HOST = 0, SBG_SCALAR_DEVICE = 1 } sbg_scalar_mode_t;
+
+typedef struct { float re, im; } sbg_cfloat;
+typedef struct { double re, im; } sbg_cdouble;
+
+/* ---- strided form: the paper's TGEMM_multi_uniform (Sec. 5) --------------
+ * Arguments, in order (positions used by sbg_last_invalid_arg):
+ *   1 transa, 2 transb   op characters (see above)
+ *   3 m, 4 n, 5 k        sizes, 0..16
+ *   6 alpha              pointer to the scalar (host or device, see mode)
+ *   7 A                  device pointer to the (0,0) element of A_0
+ *   8 lda                >= max(1, m) for op N/R, >= max(1, k) for T/C
+ *   9 strideA            elements between A_p and A_{p+1}; >= 0 (0 = one A
+ *                        shared by the whole batch)
+ *  10 B, 11 ldb (>= max(1, k) for N/R, >= max(1, n) for T/C), 12 strideB (>= 0)
+ *  13 beta
+ *  14 C, 15 ldc (>= max(1, m)), 16 strideC (>= ldc * n when batch_count > 1:
+ *     output matrices may not overlap, cf. the layout figure of Sec. 5)
+ *  17 batch_count (>= 0)
+ *  18 stream
+ */
+sbg_status_t sbg_sgemm_strided_batched(char transa, char transb, int m, int n, int k,
+    const float* alpha, const float* A, int lda, int64_t strideA,
+    const float* B, int ldb, int64_t strideB, const float* beta,
+    float* C, int ldc, int64_t strideC, int64_t batch_count, void* stream);
+sbg_status_t sbg_dgemm_strided_batched(char transa, char transb, int m, int n, int k,
+    const double* alpha, const double* A, int lda, int64_t strideA,
+    const double* B, int ldb, int64_t strideB, const double* beta,
+    double* C, int ldc, int64_t strideC, int64_t batch_count, void* stream);
+sbg_status_t sbg_cgemm_strided_batched(char transa, char transb, int m, int n, int k,
+    const sbg_cfloat* alpha, const sbg_cfloat* A, int lda, int64_t strideA,
+    const sbg_cfloat* B, int ldb, int64_t strideB, const sbg_cfloat* beta,
+    sbg_cfloat* C, int ldc, int64_t strideC, int64_t batch_count, void* stream);
+sbg_status_t sbg_zgemm_strided_batched(char transa, char transb, int m, int n, int k,
+    const sbg_cdouble* alpha, const sbg_cdouble* A, int lda, int64_t strideA,
+    const sbg_cdouble* B, int ldb, int64_t strideB, const sbg_cdouble* beta,
+    sbg_cdouble* C, int ldc, int64_t strideC, int64_t batch_count, void* stream);
+
+/* ---- pointer-array form: the paper's TGEMM_multi_nounif (Sec. 3-5) --------
+ * Same semantics with per-matrix device pointers instead of strides: A_p is
+ * Aarray[p] etc.  Aarray, Barray, Carray are device arrays of batch_count
+ * device pointers.  Positions: 1 transa, 2 transb, 3 m, 4 n, 5 k, 6 alpha,
+ * 7 Aarray, 8 lda, 9 Barray, 10 ldb, 11 beta, 12 Carray, 13 ldc,
+ * 14 batch_count, 15 stream.  Distinct Carray entries must not overlap
+ * (not checked: the pointers live on the device). */
+sbg_status_t sbg_sgemm_batched(char transa, char transb, int m, int n, int k,
+    const float* alpha, const float* const* Aarray, int lda,
+    const float* const* Barray, int ldb, const float* beta,
+    float* const* Carray, int ldc, int64_t batch_count, void* stream);
+sbg_status_t sbg_dgemm_batched(char transa, char transb, int m, int n, int k,
+    const double* alpha, const double* const* Aarray, int lda,
+    const double* const* Barray, int ldb, const double* beta,
+    double* const* Carray, int ldc, int64_t batch_count, void* stream);
+sbg_status_t sbg_cgemm_batched(char transa, char transb, int m, int n, int k,
+    const sbg_cfloat* alpha, const sbg_cfloat* const* Aarray, int lda,
+    const sbg_cfloat* const* Barray, int ldb, const sbg_cfloat* beta,
+    sbg_cfloat* const* Carray, int ldc, int64_t batch_count, void* stream);
+sbg_status_t sbg_zgemm_batched(char transa, char transb, int m, int n, int k,
+    const sbg_cdouble* alpha, const sbg_cdouble* const* Aarray, int lda,
+    const sbg_cdouble* const* Barray, int ldb, const sbg_cdouble* beta,
+    sbg_cdouble* const* Carray, int ldc, int64_t batch_count, void* stream);
+
+/* ---- library state ----------------------------------------------------------
+ * sbg_set_scalar_mode: where alpha/beta live for calls made later by the
+ *   calling thread (thread-local; default SBG_SCALAR_HOST).  In DEVICE mode the
+ *   kernels read the scalars when they run, so a captured graph can be replayed
+ *   with new values; the host-side quick returns on alpha/beta are skipped.
+ * sbg_last_invalid_arg: 1-based position of the argument rejected by the
+ *   calling thread's last SBG_INVALID_VALUE (0 if none).
+ * sbg_status_string: static text for a status code.
+ * sbg_version: library version as major*10000 + minor*100 + patch. */
+void sbg_set_scalar_mode(sbg_scalar_mode_t mode);
+sbg_scalar_mode_t sbg_get_scalar_mode(void);
+int sbg_last_invalid_arg(void);
+const char* sbg_status_string(sbg_status_t status);
+int sbg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBG_H */

@@ -1,0 +1,298 @@
+// C-ABI entry points of include/sbg.h: argument checking in BLAS (xerbla)
+// order, quick returns, decoding of the op characters (Sec. 2) and of the
+// storage rule of Sec. 5 into element strides, then one kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
+#include "sbg.h"
+#include "sbg_internal.h"
+
+namespace sbg {
+
+static thread_local sbg_scalar_mode_t tl_scalar_mode = SBG_SCALAR_HOST;
+static thread_local int tl_last_invalid = 0;
+
+int device_cu_count()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+const Tuning& tuning()
+{
+    static const Tuning t = [] {
+        Tuning v{8, 16};
+        if (const char* e = std::getenv("SBG_WG_PER_CU")) {
+            int x = std::atoi(e);
+            if (x >= 1 && x <= 32) v.wg_per_cu = x;
+        }
+        if (const char* e = std::getenv("SBG_XCD_CHUNK")) {
+            int x = std::atoi(e);
+            if (x >= 1) v.xcd_chunk = x;
+        }
+        return v;
+    }();
+    return t;
+}
+
+namespace {
+
+enum Op { OP_N, OP_T, OP_C, OP_R, OP_BAD };
+
+Op decode_op(char c)
+{
+    switch (c) {
+    case 'N': case 'n': return OP_N;
+    case 'T': case 't': return OP_T;
+    case 'C': case 'c': return OP_C;
+    case 'R': case 'r': return OP_R;
+    default: return OP_BAD;
+    }
+}
+
+bool transposes(Op o) { return o == OP_T || o == OP_C; }
+bool conjugates(Op o) { return o == OP_C || o == OP_R; }
+
+template <typename T> struct Scal;
+template <> struct Scal<float> {
+    using api_t = float;
+    static float get(const float* p) { return *p; }
+    static bool zero(float v) { return v == 0.f; }
+    static bool one(float v) { return v == 1.f; }
+};
+template <> struct Scal<double> {
+    using api_t = double;
+    static double get(const double* p) { return *p; }
+    static bool zero(double v) { return v == 0.0; }
+    static bool one(double v) { return v == 1.0; }
+};
+template <> struct Scal<float2> {
+    using api_t = sbg_cfloat;
+    static float2 get(const sbg_cfloat* p) { return make_float2(p->re, p->im); }
+    static bool zero(float2 v) { return v.x == 0.f && v.y == 0.f; }
+    static bool one(float2 v) { return v.x == 1.f && v.y == 0.f; }
+};
+template <> struct Scal<double2> {
+    using api_t = sbg_cdouble;
+    static double2 get(const sbg_cdouble* p) { return make_double2(p->re, p->im); }
+    static bool zero(double2 v) { return v.x == 0.0 && v.y == 0.0; }
+    static bool one(double2 v) { return v.x == 1.0 && v.y == 0.0; }
+};
+
+sbg_status_t reject(int pos)
+{
+    tl_last_invalid = pos;
+    return SBG_INVALID_VALUE;
+}
+
+// Common checks and launch for both batch forms.  `pos` gives the 1-based
+// argument positions of (alpha, A, lda, B, ldb, beta, C, ldc, batch) in the
+// public signature; strided-only arguments are checked by the caller.
+struct Pos { int alpha, A, lda, B, ldb, beta, C, ldc, batch; };
+
+template <typename T>
+sbg_status_t run(char transa, char transb, int m, int n, int k,
+                 const typename Scal<T>::api_t* alpha, const void* A, int lda,
+                 const void* B, int ldb, const typename Scal<T>::api_t* beta,
+                 const void* C, int ldc, int64_t batch, const Pos& pos,
+                 GemmArgs<T>& args, bool pointer_form, void* stream,
+                 const int64_t* strides /* strideA, strideB, strideC or null */)
+{
+    tl_last_invalid = 0;
+    const Op oa = decode_op(transa), ob = decode_op(transb);
+    if (oa == OP_BAD) return reject(1);
+    if (ob == OP_BAD) return reject(2);
+    if (m < 0) return reject(3);
+    if (n < 0) return reject(4);
+    if (k < 0) return reject(5);
+    if (!alpha) return reject(pos.alpha);
+    const bool host = tl_scalar_mode == SBG_SCALAR_HOST;
+    T al{}, be{};
+    if (host) al = Scal<T>::get(alpha);
+    const bool need_ab = !host || (!Scal<T>::zero(al) && k > 0);
+    const int rowsA = transposes(oa) ? k : m;
+    const int rowsB = transposes(ob) ? n : k;
+    const bool nonempty = m > 0 && n > 0 && batch > 0;
+    if (need_ab && nonempty && !A) return reject(pos.A);
+    if (lda < (rowsA > 1 ? rowsA : 1)) return reject(pos.lda);
+    if (strides && strides[0] < 0) return reject(pos.lda + 1);
+    if (need_ab && nonempty && !B) return reject(pos.B);
+    if (ldb < (rowsB > 1 ? rowsB : 1)) return reject(pos.ldb);
+    if (strides && strides[1] < 0) return reject(pos.ldb + 1);
+    if (!beta) return reject(pos.beta);
+    if (nonempty && !C) return reject(pos.C);
+    if (ldc < (m > 1 ? m : 1)) return reject(pos.ldc);
+    if (strides && (strides[2] < 0 || (batch > 1 && strides[2] < (int64_t)ldc * n)))
+        return reject(pos.ldc + 1);
+    if (batch < 0) return reject(pos.batch);
+    if (m > 16 || n > 16 || k > 16) return SBG_NOT_SUPPORTED;
+
+    if (!nonempty) return SBG_OK;
+    if (host) {
+        be = Scal<T>::get(beta);
+        if ((Scal<T>::zero(al) || k == 0) && Scal<T>::one(be)) return SBG_OK;
+    }
+
+    args.m = m;
+    args.n = n;
+    args.k = k;
+    args.lda = lda;
+    args.ldb = ldb;
+    args.ldc = ldc;
+    args.a_trans = transposes(oa);
+    args.b_trans = transposes(ob);
+    args.a_conj = conjugates(oa) ? -1.f : 1.f;
+    args.b_conj = conjugates(ob) ? -1.f : 1.f;
+    args.batch = batch;
+    if (host) {
+        args.alpha = al;
+        args.beta = be;
+        args.alpha_dev = nullptr;
+        args.beta_dev = nullptr;
+    } else {
+        args.alpha = T{};
+        args.beta = T{};
+        args.alpha_dev = reinterpret_cast<const T*>(alpha);
+        args.beta_dev = reinterpret_cast<const T*>(beta);
+    }
+    hipError_t e = launch_gemm<T>(args, pointer_form, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+template <typename T>
+sbg_status_t strided(char ta, char tb, int m, int n, int k, const typename Scal<T>::api_t* alpha,
+                     const void* A, int lda, int64_t sA, const void* B, int ldb, int64_t sB,
+                     const typename Scal<T>::api_t* beta, void* C, int ldc, int64_t sC,
+                     int64_t batch, void* stream)
+{
+    GemmArgs<T> a{};
+    a.A = static_cast<const T*>(A);
+    a.B = static_cast<const T*>(B);
+    a.C = static_cast<T*>(C);
+    a.strideA = sA;
+    a.strideB = sB;
+    a.strideC = sC;
+    const int64_t strides[3] = {sA, sB, sC};
+    static const Pos pos = {6, 7, 8, 10, 11, 13, 14, 15, 17};
+    return run<T>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, pos, a, false,
+                  stream, strides);
+}
+
+template <typename T>
+sbg_status_t pointers(char ta, char tb, int m, int n, int k, const typename Scal<T>::api_t* alpha,
+                      const void* Aarr, int lda, const void* Barr, int ldb,
+                      const typename Scal<T>::api_t* beta, const void* Carr, int ldc,
+                      int64_t batch, void* stream)
+{
+    GemmArgs<T> a{};
+    a.Aarr = static_cast<const T* const*>(Aarr);
+    a.Barr = static_cast<const T* const*>(Barr);
+    a.Carr = static_cast<T* const*>(const_cast<void*>(Carr));
+    static const Pos pos = {6, 7, 8, 9, 10, 11, 12, 13, 14};
+    return run<T>(ta, tb, m, n, k, alpha, Aarr, lda, Barr, ldb, beta, Carr, ldc, batch, pos, a, true,
+                  stream, nullptr);
+}
+
+}  // namespace
+}  // namespace sbg
+
+using sbg::pointers;
+using sbg::strided;
+
+extern "C" {
+
+sbg_status_t sbg_sgemm_strided_batched(char ta, char tb, int m, int n, int k, const float* alpha,
+    const float* A, int lda, int64_t sA, const float* B, int ldb, int64_t sB, const float* beta,
+    float* C, int ldc, int64_t sC, int64_t batch, void* stream)
+{
+    return strided<float>(ta, tb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, stream);
+}
+
+sbg_status_t sbg_dgemm_strided_batched(char ta, char tb, int m, int n, int k, const double* alpha,
+    const double* A, int lda, int64_t sA, const double* B, int ldb, int64_t sB, const double* beta,
+    double* C, int ldc, int64_t sC, int64_t batch, void* stream)
+{
+    return strided<double>(ta, tb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, stream);
+}
+
+sbg_status_t sbg_cgemm_strided_batched(char ta, char tb, int m, int n, int k, const sbg_cfloat* alpha,
+    const sbg_cfloat* A, int lda, int64_t sA, const sbg_cfloat* B, int ldb, int64_t sB,
+    const sbg_cfloat* beta, sbg_cfloat* C, int ldc, int64_t sC, int64_t batch, void* stream)
+{
+    return strided<float2>(ta, tb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, stream);
+}
+
+sbg_status_t sbg_zgemm_strided_batched(char ta, char tb, int m, int n, int k, const sbg_cdouble* alpha,
+    const sbg_cdouble* A, int lda, int64_t sA, const sbg_cdouble* B, int ldb, int64_t sB,
+    const sbg_cdouble* beta, sbg_cdouble* C, int ldc, int64_t sC, int64_t batch, void* stream)
+{
+    return strided<double2>(ta, tb, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, stream);
+}
+
+sbg_status_t sbg_sgemm_batched(char ta, char tb, int m, int n, int k, const float* alpha,
+    const float* const* A, int lda, const float* const* B, int ldb, const float* beta,
+    float* const* C, int ldc, int64_t batch, void* stream)
+{
+    return pointers<float>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+sbg_status_t sbg_dgemm_batched(char ta, char tb, int m, int n, int k, const double* alpha,
+    const double* const* A, int lda, const double* const* B, int ldb, const double* beta,
+    double* const* C, int ldc, int64_t batch, void* stream)
+{
+    return pointers<double>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+sbg_status_t sbg_cgemm_batched(char ta, char tb, int m, int n, int k, const sbg_cfloat* alpha,
+    const sbg_cfloat* const* A, int lda, const sbg_cfloat* const* B, int ldb, const sbg_cfloat* beta,
+    sbg_cfloat* const* C, int ldc, int64_t batch, void* stream)
+{
+    return pointers<float2>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+sbg_status_t sbg_zgemm_batched(char ta, char tb, int m, int n, int k, const sbg_cdouble* alpha,
+    const sbg_cdouble* const* A, int lda, const sbg_cdouble* const* B, int ldb, const sbg_cdouble* beta,
+    sbg_cdouble* const* C, int ldc, int64_t batch, void* stream)
+{
+    return pointers<double2>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+void sbg_set_scalar_mode(sbg_scalar_mode_t mode)
+{
+    sbg::tl_scalar_mode = (mode == SBG_SCALAR_DEVICE) ? SBG_SCALAR_DEVICE : SBG_SCALAR_HOST;
+}
+
+sbg_scalar_mode_t sbg_get_scalar_mode(void) { return sbg::tl_scalar_mode; }
+
+int sbg_last_invalid_arg(void) { return sbg::tl_last_invalid; }
+
+const char* sbg_status_string(sbg_status_t s)
+{
+    switch (s) {
+    case SBG_OK: return "success";
+    case SBG_INVALID_VALUE: return "invalid argument (see sbg_last_invalid_arg)";
+    case SBG_NOT_SUPPORTED: return "not supported (a size above 16)";
+    case SBG_HIP_ERROR: return "HIP runtime error at launch";
+    case SBG_WORKSPACE_TOO_SMALL: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+int sbg_version(void) { return 100; }
+
+}  // extern "C"

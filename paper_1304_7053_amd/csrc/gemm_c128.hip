@@ -1,0 +1,4 @@
+// Kernel instances for element type double2 (all size classes, both batch forms).
+#include "gemm_mfma.h"
+
+SBG_INSTANTIATE_GEMM(double2)

@@ -1,0 +1,4 @@
+// Kernel instances for element type float (all size classes, both batch forms).
+#include "gemm_mfma.h"
+
+SBG_INSTANTIATE_GEMM(float)

@@ -1,0 +1,151 @@
+"""Python binding of the C-ABI library libsbg.so (include/sbg.h).
+
+Argument marshalling only: torch supplies device memory and the current
+stream; every step of the batched GEMM runs in the library's HIP kernels.
+There is no CPU or PyTorch fallback -- if the library is missing, load()
+raises.
+
+Two call styles:
+  * the raw C-ABI names (sbg_sgemm_strided_batched, ...) taking device
+    pointers as integers, exposed through `lib()`;
+  * tensor helpers (gemm_strided, gemm_batched) that take flat device tensors
+    holding column-major batches and pass torch's current stream.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbg.so")
+
+SBG_OK, SBG_INVALID_VALUE, SBG_NOT_SUPPORTED, SBG_HIP_ERROR, SBG_WORKSPACE_TOO_SMALL = range(5)
+SCALAR_HOST, SCALAR_DEVICE = 0, 1
+
+_PREFIX = {torch.float32: "s", torch.float64: "d", torch.complex64: "c", torch.complex128: "z"}
+_REAL = {torch.float32: ctypes.c_float, torch.float64: ctypes.c_double,
+         torch.complex64: ctypes.c_float, torch.complex128: ctypes.c_double}
+
+_lib = None
+
+EXPORTS = [
+    "sbg_sgemm_strided_batched", "sbg_dgemm_strided_batched",
+    "sbg_cgemm_strided_batched", "sbg_zgemm_strided_batched",
+    "sbg_sgemm_batched", "sbg_dgemm_batched", "sbg_cgemm_batched", "sbg_zgemm_batched",
+    "sbg_set_scalar_mode", "sbg_get_scalar_mode", "sbg_last_invalid_arg",
+    "sbg_status_string", "sbg_version",
+]
+
+
+class SbgError(RuntimeError):
+    def __init__(self, status, where, arg=0):
+        self.status = status
+        self.arg = arg
+        msg = f"{where}: status {status} ({_lib.sbg_status_string(status).decode() if _lib else '?'})"
+        if status == SBG_INVALID_VALUE:
+            msg += f", argument {arg}"
+        super().__init__(msg)
+
+
+def load():
+    """Load libsbg.so (built in-tree by the package build step)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_char, i64, vp = ctypes.c_int, ctypes.c_char, ctypes.c_int64, ctypes.c_void_p
+    for p in "sdcz":
+        f = getattr(lib, f"sbg_{p}gemm_strided_batched")
+        f.argtypes = [c_char, c_char, c_int, c_int, c_int, vp, vp, c_int, i64, vp, c_int, i64,
+                      vp, vp, c_int, i64, i64, vp]
+        f.restype = c_int
+        f = getattr(lib, f"sbg_{p}gemm_batched")
+        f.argtypes = [c_char, c_char, c_int, c_int, c_int, vp, vp, c_int, vp, c_int, vp, vp, c_int,
+                      i64, vp]
+        f.restype = c_int
+    lib.sbg_set_scalar_mode.argtypes = [c_int]
+    lib.sbg_get_scalar_mode.restype = c_int
+    lib.sbg_last_invalid_arg.restype = c_int
+    lib.sbg_status_string.argtypes = [c_int]
+    lib.sbg_status_string.restype = ctypes.c_char_p
+    lib.sbg_version.restype = c_int
+    _lib = lib
+    return lib
+
+
+def lib():
+    return load()
+
+
+def _scalar_buf(value, dtype):
+    """Host buffer holding a scalar in the library's layout (re, im for complex)."""
+    rt = _REAL[dtype]
+    if dtype.is_complex:
+        v = complex(value)
+        return (rt * 2)(v.real, v.imag)
+    return (rt * 1)(float(value.real if isinstance(value, complex) else value))
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _check(status, where):
+    if status != SBG_OK:
+        raise SbgError(status, where, _lib.sbg_last_invalid_arg())
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def gemm_strided(transa, transb, m, n, k, alpha, A, lda, strideA, B, ldb, strideB, beta, C, ldc,
+                 strideC, batch, stream=None, check=True):
+    """C-ABI strided form on flat device tensors (element offsets, column-major).
+    alpha/beta are Python scalars (host mode) or 1-element device tensors
+    (device mode, switched on for the duration of the call)."""
+    L = load()
+    dtype = C.dtype
+    f = getattr(L, f"sbg_{_PREFIX[dtype]}gemm_strided_batched")
+    dev_scalars = isinstance(alpha, torch.Tensor)
+    if dev_scalars:
+        al, be = ctypes.c_void_p(alpha.data_ptr()), ctypes.c_void_p(beta.data_ptr())
+        L.sbg_set_scalar_mode(SCALAR_DEVICE)
+    else:
+        al, be = _scalar_buf(alpha, dtype), _scalar_buf(beta, dtype)
+    try:
+        st = f(transa.encode(), transb.encode(), m, n, k, ctypes.cast(al, ctypes.c_void_p) if not dev_scalars else al,
+               _dptr(A), lda, strideA, _dptr(B), ldb, strideB,
+               ctypes.cast(be, ctypes.c_void_p) if not dev_scalars else be,
+               _dptr(C), ldc, strideC, batch, _stream(stream))
+    finally:
+        if dev_scalars:
+            L.sbg_set_scalar_mode(SCALAR_HOST)
+    if check:
+        _check(st, "gemm_strided")
+    return st
+
+
+def gemm_batched(transa, transb, m, n, k, alpha, Aptrs, lda, Bptrs, ldb, beta, Cptrs, ldc, batch,
+                 dtype, stream=None, check=True):
+    """C-ABI pointer-array form; Aptrs/Bptrs/Cptrs are int64 device tensors of
+    device addresses."""
+    L = load()
+    f = getattr(L, f"sbg_{_PREFIX[dtype]}gemm_batched")
+    al, be = _scalar_buf(alpha, dtype), _scalar_buf(beta, dtype)
+    st = f(transa.encode(), transb.encode(), m, n, k, ctypes.cast(al, ctypes.c_void_p),
+           _dptr(Aptrs), lda, _dptr(Bptrs), ldb, ctypes.cast(be, ctypes.c_void_p), _dptr(Cptrs), ldc,
+           batch, _stream(stream))
+    if check:
+        _check(st, "gemm_batched")
+    return st
+
+
+def last_invalid_arg():
+    return load().sbg_last_invalid_arg()
