@@ -32,12 +32,32 @@ ALPHA, BETA = 1.5, -0.5
 METRIC = "batched GEMM GFLOP/s + % HBM roofline, n≤16, N=1e5; mixed/var-size vs plain FP32"
 
 
-def size_class(n):
-    return 4 if n <= 4 else (8 if n <= 8 else 16)
+def kernel_source_hash():
+    """Hash of the HIP sources, to tell whether stored counter readings still
+    describe the kernels being timed."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1304_7053_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def kernel_name(dt, n):
-    return f"gemm_mfma_kernel<{dt}, D={size_class(n)}, strided>"
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy), or None when the
+    summary is for another kernel or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "gemm_sizesweep_hbm_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel") != kernel or d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
 
 
 def parse():
@@ -48,6 +68,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10000,
                     help="matrices per (dtype, n, op) call timed on the CPU oracle")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed region, copy 1 GiB once (reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -79,9 +101,11 @@ def main():
                 A = torch.rand(el, generator=gen, device=dev, dtype=tdt) * 2 - 1
                 B = torch.rand(el, generator=gen, device=dev, dtype=tdt) * 2 - 1
                 C = torch.rand(el, generator=gen, device=dev, dtype=tdt) * 2 - 1
+                kname = sbg.describe_strided("s" if esz == 4 else "d", ops[0], ops[1], n, n, n, n, n * n,
+                                             n, n * n, n, n * n, N_BATCH)
                 calls.append(dict(dt=dt_name, tdt=tdt, esz=esz, n=n, ops=ops, A=A, B=B, C=C,
                                   flops=2.0 * n ** 3 * N_BATCH, bytes=4.0 * n * n * esz * N_BATCH,
-                                  kernel=kernel_name(dt_name, n)))
+                                  kernel=kname))
     torch.cuda.synchronize()
 
     def launch(c):
@@ -106,6 +130,16 @@ def main():
             ev[s][i][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    calib = None
+    if args.calib_copy:
+        src = torch.rand(1 << 28, generator=gen, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"kernel": "torch copy_ of 1 GiB float32", "bytes_read": 1 << 30, "bytes_written": 1 << 30}
+        del src, dst
 
     flops_step = sum(c["flops"] for c in calls)
     bytes_step = sum(c["bytes"] for c in calls)
@@ -166,12 +200,14 @@ def main():
         "hbm_frac_step": round(bytes_step * args.steps / elapsed / HBM_PEAK, 4),
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved * 1e9 / HBM_PEAK, 4),
-                     "traffic": None, "mean_launch_us": round(dom_avg_s * 1e6, 3),
+                     "traffic": stored_traffic(dom_name), "mean_launch_us": round(dom_avg_s * 1e6, 3),
                      "launches": dom["launches"], "algorithmic_bytes_per_launch": dom_bytes},
         "fp32_n16": head,
         "per_size": sizes_out,
         "cpu_baseline": cpu,
     }
+    if calib:
+        out["calib_copy"] = calib
     print(json.dumps(out), flush=True)
 
 

@@ -137,6 +137,18 @@ int sbg_last_invalid_arg(void);
 const char* sbg_status_string(sbg_status_t status);
 int sbg_version(void);
 
+/* ---- diagnostics --------------------------------------------------------
+ * sbg_describe_strided: validates the arguments of a strided call (prefix
+ *   's', 'd', 'c' or 'z' selects the entry point; alpha = 1, beta = 0.5 are
+ *   assumed) and writes into buf the demangled symbol of the kernel that call
+ *   would launch, as profilers report it.  Launches nothing, touches no device
+ *   memory.  Returns 0, or -1 when the call would be rejected or return early
+ *   (buf is then empty).  For benchmarks and profilers that attribute time to
+ *   kernels. */
+int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, int k, int lda,
+                         int64_t strideA, int ldb, int64_t strideB, int ldc, int64_t strideC,
+                         int64_t batch_count, char* buf, int buflen);
+
 #ifdef __cplusplus
 }
 #endif

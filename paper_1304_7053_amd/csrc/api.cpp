@@ -36,7 +36,7 @@ int device_cu_count()
 const Tuning& tuning()
 {
     static const Tuning t = [] {
-        Tuning v{8, 16};
+        Tuning v{8, 16, false};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;
@@ -45,6 +45,7 @@ const Tuning& tuning()
             int x = std::atoi(e);
             if (x >= 1) v.xcd_chunk = x;
         }
+        if (const char* e = std::getenv("SBG_STAGED")) v.staged = std::atoi(e) != 0;
         return v;
     }();
     return t;
@@ -93,6 +94,11 @@ template <> struct Scal<double2> {
     static bool zero(double2 v) { return v.x == 0.0 && v.y == 0.0; }
     static bool one(double2 v) { return v.x == 1.0 && v.y == 0.0; }
 };
+
+// When non-null, run() stops after validation and writes the name of the
+// kernel it would launch here instead of launching (thread-local).
+thread_local char* tl_describe_buf = nullptr;
+thread_local int tl_describe_len = 0;
 
 sbg_status_t reject(int pos)
 {
@@ -169,6 +175,10 @@ sbg_status_t run(char transa, char transb, int m, int n, int k,
         args.beta = T{};
         args.alpha_dev = reinterpret_cast<const T*>(alpha);
         args.beta_dev = reinterpret_cast<const T*>(beta);
+    }
+    if (tl_describe_buf) {
+        describe_gemm<T>(args, pointer_form, tl_describe_buf, tl_describe_len);
+        return SBG_OK;
     }
     hipError_t e = launch_gemm<T>(args, pointer_form, reinterpret_cast<hipStream_t>(stream));
     return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
@@ -270,6 +280,38 @@ sbg_status_t sbg_zgemm_batched(char ta, char tb, int m, int n, int k, const sbg_
     sbg_cdouble* const* C, int ldc, int64_t batch, void* stream)
 {
     return pointers<double2>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, int k, int lda,
+                         int64_t strideA, int ldb, int64_t strideB, int ldc, int64_t strideC,
+                         int64_t batch_count, char* buf, int buflen)
+{
+    if (!buf || buflen <= 0) return -1;
+    buf[0] = 0;
+    // fake, never dereferenced operand addresses: the describe path returns
+    // before any launch
+    const double one[2] = {1.0, 0.0}, half[2] = {0.5, 0.0};
+    const float onef[2] = {1.f, 0.f}, halff[2] = {0.5f, 0.f};
+    void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(256));
+    sbg::tl_describe_buf = buf;
+    sbg::tl_describe_len = buflen;
+    sbg_status_t st = SBG_INVALID_VALUE;
+    switch (prefix) {
+    case 's': st = sbg_sgemm_strided_batched(transa, transb, m, n, k, onef, (const float*)fake, lda, strideA,
+                   (const float*)fake, ldb, strideB, halff, (float*)fake, ldc, strideC, batch_count, nullptr); break;
+    case 'd': st = sbg_dgemm_strided_batched(transa, transb, m, n, k, one, (const double*)fake, lda, strideA,
+                   (const double*)fake, ldb, strideB, half, (double*)fake, ldc, strideC, batch_count, nullptr); break;
+    case 'c': st = sbg_cgemm_strided_batched(transa, transb, m, n, k, (const sbg_cfloat*)onef,
+                   (const sbg_cfloat*)fake, lda, strideA, (const sbg_cfloat*)fake, ldb, strideB,
+                   (const sbg_cfloat*)halff, (sbg_cfloat*)fake, ldc, strideC, batch_count, nullptr); break;
+    case 'z': st = sbg_zgemm_strided_batched(transa, transb, m, n, k, (const sbg_cdouble*)one,
+                   (const sbg_cdouble*)fake, lda, strideA, (const sbg_cdouble*)fake, ldb, strideB,
+                   (const sbg_cdouble*)half, (sbg_cdouble*)fake, ldc, strideC, batch_count, nullptr); break;
+    default: break;
+    }
+    sbg::tl_describe_buf = nullptr;
+    sbg::tl_describe_len = 0;
+    return st == SBG_OK && buf[0] ? 0 : -1;
 }
 
 void sbg_set_scalar_mode(sbg_scalar_mode_t mode)

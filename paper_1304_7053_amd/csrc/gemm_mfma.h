@@ -36,6 +36,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <cstdio>
 
 #include "sbg_internal.h"
 
@@ -150,7 +151,6 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
 
     // Persistent traversal with XCD-aware renumbering (gridDim.x % 8 == 0).
     const int64_t W = (int64_t)gridDim.x * 4;
-    const int64_t Wx = W >> 3;
     const int64_t local = (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
     const int64_t xcd = blockIdx.x & 7;
     const int64_t S = a.xcd_chunk;
@@ -310,16 +310,31 @@ template <typename T, int D> struct Unroll {
     static constexpr int value = per_tile >= 6144 ? 1 : (per_tile >= 3072 ? 2 : 4);
 };
 
-template <typename T, int D, bool ACONT, bool BCONT, bool PTR>
-hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
+// Work-groups that fit on one CU at once (registers and LDS), cached per kernel.
+template <typename K>
+inline int resident_per_cu(K kernel)
 {
-    constexpr int U = Unroll<T, D>::value;
-    constexpr int P = 16 / D;
+    static int cached = 0;
+    if (cached == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+        cached = nb;
+    }
+    return cached;
+}
+
+// Persistent grid for `units` independent wave-sized work units: at most the
+// resident work-groups (capped by the tuning knob), a multiple of 8 so the
+// XCD renumbering is exact; sets the XCD run length to a divisor of the
+// waves per XCD.
+template <typename T, typename K>
+inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
+{
     const Tuning& tu = tuning();
-    const int64_t tiles = (a.batch + P - 1) / P;
-    const int64_t groups = (tiles + U - 1) / U;
-    const int64_t wg_needed = (groups + 3) / 4;
-    const int64_t cap = (int64_t)device_cu_count() * tu.wg_per_cu;
+    int per_cu = resident_per_cu(kernel);
+    if (per_cu > tu.wg_per_cu) per_cu = tu.wg_per_cu;
+    const int64_t wg_needed = (units + 3) / 4;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
     int64_t grid = wg_needed < cap ? wg_needed : cap;
     grid = ((grid + 7) / 8) * 8;
     const int64_t wx = grid / 8 * 4;   // waves per XCD
@@ -327,14 +342,37 @@ hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
     if (s > wx) s = wx;
     while (wx % s) --s;
     a.xcd_chunk = s;
-    hipLaunchKernelGGL((gemm_mfma_kernel<T, D, U, ACONT, BCONT, PTR>), dim3((unsigned)grid), dim3(256), 0,
-                       stream, a);
+    return grid;
+}
+
+template <typename T, int D, bool ACONT, bool BCONT, bool PTR>
+hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
+{
+    constexpr int U = Unroll<T, D>::value;
+    constexpr int P = 16 / D;
+    auto kern = gemm_mfma_kernel<T, D, U, ACONT, BCONT, PTR>;
+    const int64_t tiles = (a.batch + P - 1) / P;
+    const int64_t groups = (tiles + U - 1) / U;
+    const int64_t grid = persistent_grid(kern, groups, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
+
+template <typename T, int D, bool ACONT, bool BCONT>
+hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream);
+template <typename T>
+int staged_run_length(int m, int n, int k, int64_t batch, int min_waves);
 
 template <typename T, int D, bool PTR>
 hipError_t launch_ops(const GemmArgs<T>& a, hipStream_t stream)
 {
+    if (!PTR && a.G > 0) {
+        if (a.a_trans)
+            return a.b_trans ? launch_staged<T, D, true, false>(a, stream)
+                             : launch_staged<T, D, true, true>(a, stream);
+        return a.b_trans ? launch_staged<T, D, false, false>(a, stream)
+                         : launch_staged<T, D, false, true>(a, stream);
+    }
     const bool at = a.a_trans, bn = !a.b_trans;
     if (at) {
         if (bn) return launch_variant<T, D, true, true, PTR>(a, stream);
@@ -345,8 +383,19 @@ hipError_t launch_ops(const GemmArgs<T>& a, hipStream_t stream)
 }
 
 template <typename T>
-hipError_t launch_gemm_impl(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream)
+hipError_t launch_gemm_impl(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
+    a.G = 0;
+    if (!pointer_form) {
+        // packed layout: minimal leading dimensions and strides (lda, ldb are
+        // the stored row counts, which depend on the ops)
+        const int64_t ra = a.a_trans ? a.k : a.m, ca = a.a_trans ? a.m : a.k;
+        const int64_t rb = a.b_trans ? a.n : a.k, cb = a.b_trans ? a.k : a.n;
+        const bool packed = a.k >= 1 && a.lda == ra && a.ldb == rb && a.ldc == a.m &&
+                            a.strideA == ra * ca && a.strideB == rb * cb &&
+                            a.strideC == (int64_t)a.m * a.n;
+        if (packed && tuning().staged) a.G = staged_run_length<T>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
+    }
     int mx = a.m > a.n ? a.m : a.n;
     mx = mx > a.k ? mx : a.k;
     if (pointer_form) {
@@ -359,6 +408,38 @@ hipError_t launch_gemm_impl(const GemmArgs<T>& a, bool pointer_form, hipStream_t
     return launch_ops<T, 16, false>(a, stream);
 }
 
+template <typename T> struct TypeName;
+template <> struct TypeName<float> { static constexpr const char* s = "float"; };
+template <> struct TypeName<double> { static constexpr const char* s = "double"; };
+template <> struct TypeName<float2> { static constexpr const char* s = "HIP_vector_type<float, 2u>"; };
+template <> struct TypeName<double2> { static constexpr const char* s = "HIP_vector_type<double, 2u>"; };
+
+// The kernel symbol (as profilers demangle it) a launch with these arguments
+// uses, written into buf.
+template <typename T>
+int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
+{
+    const auto tf = [](bool b) { return b ? "true" : "false"; };
+    int mx = a.m > a.n ? a.m : a.n;
+    mx = mx > a.k ? mx : a.k;
+    const int D = mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
+    int G = 0;
+    if (!pointer_form) {
+        const int64_t ra = a.a_trans ? a.k : a.m, ca = a.a_trans ? a.m : a.k;
+        const int64_t rb = a.b_trans ? a.n : a.k, cb = a.b_trans ? a.k : a.n;
+        const bool packed = a.k >= 1 && a.lda == ra && a.ldb == rb && a.ldc == a.m &&
+                            a.strideA == ra * ca && a.strideB == rb * cb &&
+                            a.strideC == (int64_t)a.m * a.n;
+        if (packed && tuning().staged) G = 1;
+    }
+    if (G)
+        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %d, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
+    const int U = D == 4 ? Unroll<T, 4>::value : (D == 8 ? Unroll<T, 8>::value : Unroll<T, 16>::value);
+    return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %d, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
+                    TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form), TypeName<T>::s);
+}
+
 }  // namespace sbg
 
 #define SBG_INSTANTIATE_GEMM(T)                                                      \
@@ -367,5 +448,10 @@ hipError_t launch_gemm_impl(const GemmArgs<T>& a, bool pointer_form, hipStream_t
     hipError_t launch_gemm<T>(const GemmArgs<T>& a, bool pointer_form, hipStream_t s) \
     {                                                                                \
         return launch_gemm_impl<T>(a, pointer_form, s);                              \
+    }                                                                                \
+    template <>                                                                      \
+    int describe_gemm<T>(const GemmArgs<T>& a, bool pointer_form, char* buf, int len) \
+    {                                                                                \
+        return describe_gemm_impl<T>(a, pointer_form, buf, len);                     \
     }                                                                                \
     }

@@ -35,19 +35,25 @@ struct GemmArgs {
     float a_conj, b_conj;
     int64_t batch;
     int64_t xcd_chunk;   // consecutive tile groups per XCD run (set by the launcher)
+    int G;               // matrices per wave step of the LDS-staged kernel
 };
 
-// Launch-shape knobs: work-groups per CU of the persistent grid and the XCD
-// run length.  Defaults are the tuned values; SBG_WG_PER_CU and
-// SBG_XCD_CHUNK override them (read once per process) for tuning sweeps.
+// Launch-shape knobs: work-groups per CU of the persistent grid, the XCD run
+// length and whether packed batches take the LDS-staged kernel.  Defaults
+// are the tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK and SBG_STAGED override
+// them (read once per process) for tuning sweeps and A/B comparisons.
 struct Tuning {
     int wg_per_cu;
     int xcd_chunk;
+    bool staged;   // use the LDS-staged kernel for packed strided batches
 };
 const Tuning& tuning();
 
 template <typename T>
 hipError_t launch_gemm(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream);
+
+template <typename T>
+int describe_gemm(const GemmArgs<T>& a, bool pointer_form, char* buf, int len);
 
 int device_cu_count();
 

@@ -33,7 +33,7 @@ EXPORTS = [
     "sbg_cgemm_strided_batched", "sbg_zgemm_strided_batched",
     "sbg_sgemm_batched", "sbg_dgemm_batched", "sbg_cgemm_batched", "sbg_zgemm_batched",
     "sbg_set_scalar_mode", "sbg_get_scalar_mode", "sbg_last_invalid_arg",
-    "sbg_status_string", "sbg_version",
+    "sbg_status_string", "sbg_version", "sbg_describe_strided",
 ]
 
 
@@ -71,6 +71,9 @@ def load():
     lib.sbg_status_string.argtypes = [c_int]
     lib.sbg_status_string.restype = ctypes.c_char_p
     lib.sbg_version.restype = c_int
+    lib.sbg_describe_strided.argtypes = [c_char, c_char, c_char, c_int, c_int, c_int, c_int, i64, c_int, i64,
+                                         c_int, i64, i64, ctypes.c_char_p, c_int]
+    lib.sbg_describe_strided.restype = c_int
     _lib = lib
     return lib
 
@@ -145,6 +148,15 @@ def gemm_batched(transa, transb, m, n, k, alpha, Aptrs, lda, Bptrs, ldb, beta, C
     if check:
         _check(st, "gemm_batched")
     return st
+
+
+def describe_strided(prefix, transa, transb, m, n, k, lda, strideA, ldb, strideB, ldc, strideC, batch):
+    """Demangled name of the kernel a strided call with these arguments would
+    launch (nothing is launched), or None if the call would not launch."""
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sbg_describe_strided(prefix.encode(), transa.encode(), transb.encode(), m, n, k, lda, strideA,
+                                     ldb, strideB, ldc, strideC, batch, buf, 512)
+    return buf.value.decode() if rc == 0 else None
 
 
 def last_invalid_arg():
