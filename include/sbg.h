@@ -65,6 +65,20 @@ typedef enum { SBG_SCALAR_HOST = 0, SBG_SCALAR_DEVICE = 1 } sbg_scalar_mode_t;
 typedef struct { float re, im; } sbg_cfloat;
 typedef struct { double re, im; } sbg_cdouble;
 
+/* Stored type of A and B in the mixed-precision (_ex) forms; C and the
+ * accumulation are binary32. */
+typedef enum {
+    SBG_R_32F = 0,       /* binary32 */
+    SBG_R_16BF = 1,      /* bfloat16 */
+    SBG_R_16F = 2,       /* IEEE binary16 */
+    SBG_R_8F_E4M3 = 3    /* OCP FP8 E4M3 ("fn": max 448, no infinities), per-matrix scales */
+} sbg_datatype_t;
+
+/* SBG_MODE_BF16X3: binary32 A and B are split into bfloat16 hi + lo on the fly
+ * and hi*hi + hi*lo + lo*hi is accumulated in binary32 (the lo*lo term is
+ * dropped; accuracy is about 2^-16 relative, not binary32). */
+typedef enum { SBG_MODE_PLAIN = 0, SBG_MODE_BF16X3 = 1 } sbg_compute_mode_t;
+
 /* ---- strided form: the paper's TGEMM_multi_uniform (Sec. 5) --------------
  * Arguments, in order (positions used by sbg_last_invalid_arg):
  *   1 transa, 2 transb   op characters (see above)
@@ -121,6 +135,83 @@ sbg_status_t sbg_zgemm_batched(char transa, char transb, int m, int n, int k,
     const sbg_cdouble* alpha, const sbg_cdouble* const* Aarray, int lda,
     const sbg_cdouble* const* Barray, int ldb, const sbg_cdouble* beta,
     sbg_cdouble* const* Carray, int ldc, int64_t batch_count, void* stream);
+
+/* ---- variable-size form (one call for a batch of unequal sizes) ------------
+ * Matrix p has its own sizes d_m[p], d_n[p], d_k[p] and leading dimensions
+ * d_lda[p], d_ldb[p], d_ldc[p] (device int arrays) and its own pointers, as in
+ * the pointer-array form; ops, alpha and beta are shared.  This generalises the
+ * paper's remark that unequal sizes can be partitioned into sets of equal size
+ * (Sec. 1): the partition is done on the device (size classes by max(m, n, k))
+ * and the whole batch runs as one persistent launch, so a call can be captured
+ * in a HIP graph and replayed.
+ *   max_m, max_n, max_k: host-side upper bounds of the sizes (<= 16; larger
+ *     gives SBG_NOT_SUPPORTED).  A matrix whose sizes exceed them, are
+ *     negative, or whose leading dimensions are too small is SKIPPED (its C is
+ *     untouched) and counted in the int at word 3 of the workspace.
+ *   workspace: caller-owned device memory of at least
+ *     sbg_vbatched_workspace_size(batch_count) bytes; it is overwritten on
+ *     every call, so concurrent calls need distinct workspaces.
+ * Positions: 1 transa, 2 transb, 3 d_m, 4 d_n, 5 d_k, 6 max_m, 7 max_n,
+ * 8 max_k, 9 alpha, 10 Aarray, 11 d_lda, 12 Barray, 13 d_ldb, 14 beta,
+ * 15 Carray, 16 d_ldc, 17 batch_count (<= 2^31 - 1), 18 workspace,
+ * 19 workspace_bytes (SBG_WORKSPACE_TOO_SMALL when short), 20 stream. */
+size_t sbg_vbatched_workspace_size(int64_t batch_count);
+sbg_status_t sbg_sgemm_vbatched(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const float* alpha, const float* const* Aarray, const int* d_lda,
+    const float* const* Barray, const int* d_ldb, const float* beta, float* const* Carray, const int* d_ldc,
+    int64_t batch_count, void* workspace, size_t workspace_bytes, void* stream);
+sbg_status_t sbg_dgemm_vbatched(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const double* alpha, const double* const* Aarray, const int* d_lda,
+    const double* const* Barray, const int* d_ldb, const double* beta, double* const* Carray, const int* d_ldc,
+    int64_t batch_count, void* workspace, size_t workspace_bytes, void* stream);
+sbg_status_t sbg_cgemm_vbatched(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const sbg_cfloat* alpha, const sbg_cfloat* const* Aarray, const int* d_lda,
+    const sbg_cfloat* const* Barray, const int* d_ldb, const sbg_cfloat* beta, sbg_cfloat* const* Carray,
+    const int* d_ldc, int64_t batch_count, void* workspace, size_t workspace_bytes, void* stream);
+sbg_status_t sbg_zgemm_vbatched(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const sbg_cdouble* alpha, const sbg_cdouble* const* Aarray, const int* d_lda,
+    const sbg_cdouble* const* Barray, const int* d_ldb, const sbg_cdouble* beta, sbg_cdouble* const* Carray,
+    const int* d_ldc, int64_t batch_count, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- mixed precision (binary32 accumulation and C) --------------------------
+ * A and B are stored as ab_type; with scaleA/scaleB (device float arrays of
+ * batch_count entries, both or neither; required for SBG_R_8F_E4M3) the
+ * operands are sA[p] * A_p and sB[p] * B_p, so
+ *     C_p <- alpha * sA[p] * sB[p] * op(A_p) op(B_p) + beta * C_p.
+ * Narrow inputs are decoded exactly to binary32; products of bf16, fp16 and
+ * e4m3 values are exact in binary32.  mode SBG_MODE_BF16X3 needs ab_type
+ * SBG_R_32F.  Positions of the strided form: 1 transa, 2 transb, 3 m, 4 n, 5 k,
+ * 6 alpha, 7 A, 8 lda, 9 strideA, 10 scaleA, 11 B, 12 ldb, 13 strideB,
+ * 14 scaleB, 15 beta, 16 C, 17 ldc, 18 strideC, 19 batch_count, 20 ab_type,
+ * 21 mode; of the variable-size form: as sbg_sgemm_vbatched with scaleA at 12,
+ * scaleB at 15 (B, d_ldb at 13, 14), beta 16, Carray 17, d_ldc 18,
+ * batch_count 19, ab_type 20, mode 21, workspace 22, workspace_bytes 23.
+ * Scales, type and mode are checked after the other arguments. */
+sbg_status_t sbg_gemm_strided_batched_ex(char transa, char transb, int m, int n, int k, const float* alpha,
+    const void* A, int lda, int64_t strideA, const float* scaleA,
+    const void* B, int ldb, int64_t strideB, const float* scaleB,
+    const float* beta, float* C, int ldc, int64_t strideC, int64_t batch_count,
+    sbg_datatype_t ab_type, sbg_compute_mode_t mode, void* stream);
+sbg_status_t sbg_gemm_vbatched_ex(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const float* alpha, const void* const* Aarray, const int* d_lda,
+    const float* scaleA, const void* const* Barray, const int* d_ldb, const float* scaleB, const float* beta,
+    float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type,
+    sbg_compute_mode_t mode, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- per-matrix absmax quantisation to FP8 E4M3 -----------------------------
+ * For each binary32 matrix X_p (rows x cols <= 16 x 16): s_p = max|X_p| / 448
+ * (1 for an all-zero matrix), Q_p = e4m3(X_p / s_p) rounded to nearest even and
+ * saturated to +-448; scales[p] = s_p.  The outputs feed the _ex forms with
+ * ab_type SBG_R_8F_E4M3.  Strided positions: 1 rows, 2 cols, 3 X, 4 ldx,
+ * 5 strideX, 6 Q, 7 ldq, 8 strideQ, 9 scales, 10 batch_count.  Variable-size
+ * positions: 1 d_rows, 2 d_cols, 3 max_rows, 4 max_cols, 5 Xarray, 6 d_ldx,
+ * 7 Qarray, 8 d_ldq, 9 scales, 10 batch_count; matrices with invalid sizes are
+ * skipped (scale not written). */
+sbg_status_t sbg_quantize_e4m3_strided_batched(int rows, int cols, const float* X, int ldx, int64_t strideX,
+    unsigned char* Q, int ldq, int64_t strideQ, float* scales, int64_t batch_count, void* stream);
+sbg_status_t sbg_quantize_e4m3_vbatched(const int* d_rows, const int* d_cols, int max_rows, int max_cols,
+    const float* const* Xarray, const int* d_ldx, unsigned char* const* Qarray, const int* d_ldq, float* scales,
+    int64_t batch_count, void* stream);
 
 /* ---- library state ----------------------------------------------------------
  * sbg_set_scalar_mode: where alpha/beta live for calls made later by the

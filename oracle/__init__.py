@@ -5,5 +5,5 @@ this package.  The product path (paper_1304_7053_amd) never imports it.
 """
 from .oracle import (  # noqa: F401
     TYPE_CODES, gemm, gemm_strided, gemm_general, bound_strided, bound_general,
-    set_threads, max_threads,
+    set_threads, max_threads, encode_e4m3, round_bf16, decode, quant_e4m3, gemm_split3_general,
 )

@@ -49,8 +49,18 @@
  * Complex values are (re, im) pairs.  Optional per-matrix scales multiply every
  * decoded element of A^p (scaleA[p]) or B^p (scaleB[p]) exactly.
  *
+ * Two further routines serve the precision modes:
+ *   oracle_quant_e4m3   per-matrix absmax scaling s = max|X|/448 (1 when X = 0)
+ *                       and rounding of X/s (binary32 division) to the nearest
+ *                       OCP E4M3 value, ties to even, saturating to +-448;
+ *   oracle_gemm_split3  the BF16x3 product: every binary32 operand x is split
+ *                       into hi = bf16(x), lo = bf16(x - hi) (round to nearest
+ *                       even) and sum_l hi_a hi_b + hi_a lo_b + lo_a hi_b is
+ *                       accumulated exactly as in oracle_gemm.
+ *
  * Parity status: pinned by tests/test_oracle_*.py (library cross-checks,
- * identities, closed forms, exact rational brute force).
+ * identities, closed forms, exact rational brute force, torch's float8 and
+ * bfloat16 conversions).
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -322,3 +332,130 @@ int oracle_gemm_bound(int tA, int tB, int tC, char transa, char transb, int64_t 
     }
     return 0;
 }
+
+/* ---- precision-mode helpers ------------------------------------------------ */
+
+/* Nearest bfloat16 value (8 significant bits, binary32 exponent range with
+ * subnormal spacing 2^-133), ties to even; exact in double. */
+static double round_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);                       /* x = f 2^e, 0.5 <= |f| < 1 */
+    int q = e - 8;                      /* spacing 2^q of 8-bit significands */
+    if (q < -133) q = -133;
+    return ldexp(nearbyint(ldexp(x, -q)), q);
+}
+
+/* Nearest OCP E4M3 code of a binary32 value: 3 fraction bits, exponents
+ * -6..8, subnormal spacing 2^-9, ties to even, saturation to 448 (0x7E). */
+static uint8_t encode_e4m3(float v)
+{
+    uint8_t sign = signbit(v) ? 0x80 : 0x00;
+    double a = fabs((double)v);
+    if (isnan(v)) return (uint8_t)(sign | 0x7F);
+    if (a >= 464.0) return (uint8_t)(sign | 0x7E);
+    if (a < ldexp(1.0, -6)) {
+        double m = nearbyint(a * 512.0);            /* units of 2^-9 */
+        return (uint8_t)(sign | (uint8_t)m);        /* m == 8 is the code of 2^-6 */
+    }
+    int e;
+    frexp(a, &e);
+    e -= 1;                                         /* a = 1.f * 2^e */
+    double m = nearbyint((ldexp(a, -e) - 1.0) * 8.0);
+    if (m == 8.0) { m = 0.0; e += 1; }
+    return (uint8_t)(sign | (uint8_t)((e + 7) << 3) | (uint8_t)m);
+}
+
+/*
+ * Per-matrix absmax quantisation.  Matrix p: rows[p] x cols[p] binary32 values
+ * at X[offX[p] + i + ldx[p] j]; writes codes column-major (leading dimension
+ * rows[p]) at Q[offQ[p] ...] and the scale to scales[p].
+ */
+void oracle_quant_e4m3(int64_t batch, const int32_t* rows, const int32_t* cols, const float* X,
+                       const int64_t* offX, const int32_t* ldx, uint8_t* Q, const int64_t* offQ,
+                       float* scales)
+{
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < batch; ++p) {
+        float amax = 0.0f;
+        for (int j = 0; j < cols[p]; ++j)
+            for (int i = 0; i < rows[p]; ++i) {
+                float a = fabsf(X[offX[p] + i + (int64_t)ldx[p] * j]);
+                if (a > amax) amax = a;
+            }
+        float s = amax > 0.0f ? amax / 448.0f : 1.0f;
+        scales[p] = s;
+        for (int j = 0; j < cols[p]; ++j)
+            for (int i = 0; i < rows[p]; ++i) {
+                float x = X[offX[p] + i + (int64_t)ldx[p] * j];
+                Q[offQ[p] + i + (int64_t)rows[p] * j] = encode_e4m3(x / s);
+            }
+    }
+}
+
+/* op(X)(r, c) of a binary32 matrix split into bf16 hi and lo parts. */
+static void op_split(char op, const float* X, int64_t off, int ld, int r, int c, double* hi, double* lo)
+{
+    int64_t idx = (op == 'N' || op == 'n' || op == 'R' || op == 'r') ? off + r + (int64_t)ld * c
+                                                                     : off + c + (int64_t)ld * r;
+    double x = X[idx];
+    *hi = round_bf16(x);
+    *lo = round_bf16(x - *hi);      /* x - hi is exact in double */
+}
+
+/*
+ * BF16x3 reference (real binary32 inputs and C): per entry
+ *   acc = sum_l hi_a hi_b + hi_a lo_b + lo_a hi_b   (long double, l ascending)
+ *   out = alpha acc + beta C_in   (alpha == 0: A, B unread; beta == 0: C unread)
+ * returned as hi + lo doubles; bound[] (may be NULL) receives
+ *   |alpha| sum_l (|hi_a hi_b| + |hi_a lo_b| + |lo_a hi_b|) + |beta| |C_in|.
+ * Same conventions as oracle_gemm (real types only: alpha, beta are doubles).
+ */
+int oracle_gemm_split3(char transa, char transb, int64_t batch, const int32_t* m, const int32_t* n,
+                       const int32_t* k, double alpha, double beta, const float* A, const int64_t* offA,
+                       const int32_t* lda, const float* B, const int64_t* offB, const int32_t* ldb,
+                       const float* C, const int64_t* offC, const int32_t* ldc, const int64_t* offO,
+                       double* hi, double* lo, double* bound)
+{
+    if (!op_ok(transa) || !op_ok(transb)) return -1;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < batch; ++p)
+        for (int j = 0; j < n[p]; ++j)
+            for (int i = 0; i < m[p]; ++i) {
+                long double s = 0, sb = 0;
+                if (alpha != 0.0)
+                    for (int l = 0; l < k[p]; ++l) {
+                        double ah, al, bh, bl;
+                        op_split(transa, A, offA[p], lda[p], i, l, &ah, &al);
+                        op_split(transb, B, offB[p], ldb[p], l, j, &bh, &bl);
+                        long double t1 = (long double)ah * bh;
+                        long double t2 = (long double)ah * bl;
+                        long double t3 = (long double)al * bh;
+                        s = s + t1;
+                        s = s + t2;
+                        s = s + t3;
+                        sb += fabsl(t1) + fabsl(t2) + fabsl(t3);
+                    }
+                long double c = 0;
+                if (beta != 0.0) c = C[offC[p] + i + (int64_t)ldc[p] * j];
+                long double r;
+                if (alpha == 0.0) r = beta == 0.0 ? 0.0L : (long double)beta * c;
+                else if (beta == 0.0) r = (long double)alpha * s;
+                else r = (long double)alpha * s + (long double)beta * c;
+                int64_t o = offO[p] + i + (int64_t)m[p] * j;
+                double h = (double)r;
+                hi[o] = h;
+                lo[o] = (double)(r - (long double)h);
+                if (bound)
+                    bound[o] = (double)(fabsl((long double)alpha) * sb + fabsl((long double)beta) * fabsl(c));
+            }
+    return 0;
+}
+
+/* Exposed for the pins: the encoder and the bf16 rounding on single values. */
+uint8_t oracle_encode_e4m3(float v) { return encode_e4m3(v); }
+double oracle_round_bf16(double x) { return round_bf16(x); }
+double oracle_decode_e4m3(uint8_t b) { return dec_e4m3(b); }
+double oracle_decode_f16(uint16_t h) { return dec_f16(h); }
+double oracle_decode_bf16(uint16_t h) { return dec_bf16(h); }

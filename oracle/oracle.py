@@ -32,6 +32,22 @@ def _load():
         lib.oracle_gemm.restype = ctypes.c_int
         lib.oracle_gemm_bound.argtypes = common + [dp]
         lib.oracle_gemm_bound.restype = ctypes.c_int
+        lib.oracle_quant_e4m3.argtypes = [ctypes.c_int64, i32p, i32p, vp, i64p, i32p, vp, i64p, vp]
+        lib.oracle_quant_e4m3.restype = None
+        lib.oracle_gemm_split3.argtypes = [ctypes.c_char, ctypes.c_char, ctypes.c_int64, i32p, i32p, i32p,
+                                           ctypes.c_double, ctypes.c_double, vp, i64p, i32p, vp, i64p, i32p,
+                                           vp, i64p, i32p, i64p, dp, dp, dp]
+        lib.oracle_gemm_split3.restype = ctypes.c_int
+        lib.oracle_encode_e4m3.argtypes = [ctypes.c_float]
+        lib.oracle_encode_e4m3.restype = ctypes.c_uint8
+        lib.oracle_round_bf16.argtypes = [ctypes.c_double]
+        lib.oracle_round_bf16.restype = ctypes.c_double
+        lib.oracle_decode_e4m3.argtypes = [ctypes.c_uint8]
+        lib.oracle_decode_e4m3.restype = ctypes.c_double
+        lib.oracle_decode_f16.argtypes = [ctypes.c_uint16]
+        lib.oracle_decode_f16.restype = ctypes.c_double
+        lib.oracle_decode_bf16.argtypes = [ctypes.c_uint16]
+        lib.oracle_decode_bf16.restype = ctypes.c_double
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -206,3 +222,66 @@ def gemm(transa, transb, alpha, A, B, beta, C, ext=False):
         Cf = np.zeros(batch * m * n, dtype=dt)
     return gemm_strided(transa, transb, m, n, k, alpha, Af, max(ra, 1), ra * ca, Bf, max(rb, 1),
                         rb * cb, beta, Cf, max(m, 1), m * n, batch, ext=ext)
+
+
+def encode_e4m3(v):
+    return int(_load().oracle_encode_e4m3(float(v)))
+
+
+def round_bf16(x):
+    return float(_load().oracle_round_bf16(float(x)))
+
+
+def decode(code, fmt):
+    """Value of one stored code: fmt in {'e4m3', 'f16', 'bf16'}."""
+    L = _load()
+    return float({"e4m3": L.oracle_decode_e4m3, "f16": L.oracle_decode_f16, "bf16": L.oracle_decode_bf16}[fmt](int(code)))
+
+
+def quant_e4m3(X, offX, rows, cols, ldx, batch):
+    """Per-matrix absmax E4M3 quantisation.  X: flat binary32 storage; returns
+    (codes, offQ, scales): codes packed column-major per matrix at offQ[p]."""
+    rows_ = _per(rows, batch, np.int32)
+    cols_ = _per(cols, batch, np.int32)
+    ldx_ = _per(ldx, batch, np.int32)
+    offX_ = _per(offX, batch, np.int64)
+    cnt = rows_.astype(np.int64) * cols_
+    offQ = np.zeros(batch, dtype=np.int64)
+    if batch > 1:
+        offQ[1:] = np.cumsum(cnt)[:-1]
+    Q = np.zeros(max(int(cnt.sum()), 1), dtype=np.uint8)
+    scales = np.zeros(max(batch, 1), dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    _load().oracle_quant_e4m3(batch, _ptr(rows_, ctypes.c_int32), _ptr(cols_, ctypes.c_int32), _vptr(X),
+                              _ptr(offX_, ctypes.c_int64), _ptr(ldx_, ctypes.c_int32), _vptr(Q),
+                              _ptr(offQ, ctypes.c_int64), _vptr(scales))
+    return Q, offQ, scales[:batch]
+
+
+def gemm_split3_general(transa, transb, m, n, k, alpha, A, offA, lda, B, offB, ldb, beta, C, offC, ldc, batch):
+    """BF16x3 reference on binary32 storage; returns (hi, lo, bound, offO, m, n)
+    flat, packed as gemm_general (real)."""
+    m_, n_, k_ = (_per(v, batch, np.int32) for v in (m, n, k))
+    lda_, ldb_, ldc_ = (_per(v, batch, np.int32) for v in (lda, ldb, ldc))
+    offA_, offB_, offC_ = (_per(v, batch, np.int64) for v in (offA, offB, offC))
+    cnt = m_.astype(np.int64) * n_
+    offO = np.zeros(batch, dtype=np.int64)
+    if batch > 1:
+        offO[1:] = np.cumsum(cnt)[:-1]
+    total = max(int(cnt.sum()), 1)
+    hi = np.empty(total)
+    lo = np.empty(total)
+    bound = np.empty(total)
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    C = np.ascontiguousarray(C, dtype=np.float32) if C is not None else None
+    rc = _load().oracle_gemm_split3(transa.encode(), transb.encode(), batch, _ptr(m_, ctypes.c_int32),
+                                    _ptr(n_, ctypes.c_int32), _ptr(k_, ctypes.c_int32), float(alpha), float(beta),
+                                    _vptr(A), _ptr(offA_, ctypes.c_int64), _ptr(lda_, ctypes.c_int32),
+                                    _vptr(B), _ptr(offB_, ctypes.c_int64), _ptr(ldb_, ctypes.c_int32),
+                                    _vptr(C), _ptr(offC_, ctypes.c_int64), _ptr(ldc_, ctypes.c_int32),
+                                    _ptr(offO, ctypes.c_int64), _ptr(hi, ctypes.c_double),
+                                    _ptr(lo, ctypes.c_double), _ptr(bound, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle_gemm_split3 rejected its arguments")
+    return hi, lo, bound, offO, m_, n_

@@ -111,14 +111,17 @@ sbg_status_t reject(int pos)
 // public signature; strided-only arguments are checked by the caller.
 struct Pos { int alpha, A, lda, B, ldb, beta, C, ldc, batch; };
 
+// Validates in argument order and fills args; `launch` is false on a quick
+// return.  Strides (strided form) are checked at positions lda+1, ldb+1, ldc+1.
 template <typename T>
-sbg_status_t run(char transa, char transb, int m, int n, int k,
-                 const typename Scal<T>::api_t* alpha, const void* A, int lda,
-                 const void* B, int ldb, const typename Scal<T>::api_t* beta,
-                 const void* C, int ldc, int64_t batch, const Pos& pos,
-                 GemmArgs<T>& args, bool pointer_form, void* stream,
-                 const int64_t* strides /* strideA, strideB, strideC or null */)
+sbg_status_t prepare(char transa, char transb, int m, int n, int k,
+                     const typename Scal<T>::api_t* alpha, const void* A, int lda,
+                     const void* B, int ldb, const typename Scal<T>::api_t* beta,
+                     const void* C, int ldc, int64_t batch, const Pos& pos,
+                     GemmArgs<T>& args, bool& launch,
+                     const int64_t* strides /* strideA, strideB, strideC or null */)
 {
+    launch = false;
     tl_last_invalid = 0;
     const Op oa = decode_op(transa), ob = decode_op(transb);
     if (oa == OP_BAD) return reject(1);
@@ -176,6 +179,13 @@ sbg_status_t run(char transa, char transb, int m, int n, int k,
         args.alpha_dev = reinterpret_cast<const T*>(alpha);
         args.beta_dev = reinterpret_cast<const T*>(beta);
     }
+    launch = true;
+    return SBG_OK;
+}
+
+template <typename T>
+sbg_status_t launch_plain(GemmArgs<T>& args, bool pointer_form, void* stream)
+{
     if (tl_describe_buf) {
         describe_gemm<T>(args, pointer_form, tl_describe_buf, tl_describe_len);
         return SBG_OK;
@@ -191,16 +201,19 @@ sbg_status_t strided(char ta, char tb, int m, int n, int k, const typename Scal<
                      int64_t batch, void* stream)
 {
     GemmArgs<T> a{};
-    a.A = static_cast<const T*>(A);
-    a.B = static_cast<const T*>(B);
+    a.A = A;
+    a.B = B;
     a.C = static_cast<T*>(C);
     a.strideA = sA;
     a.strideB = sB;
     a.strideC = sC;
     const int64_t strides[3] = {sA, sB, sC};
     static const Pos pos = {6, 7, 8, 10, 11, 13, 14, 15, 17};
-    return run<T>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, pos, a, false,
-                  stream, strides);
+    bool launch = false;
+    const sbg_status_t st = prepare<T>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, pos, a,
+                                       launch, strides);
+    if (st != SBG_OK || !launch) return st;
+    return launch_plain<T>(a, false, stream);
 }
 
 template <typename T>
@@ -210,13 +223,118 @@ sbg_status_t pointers(char ta, char tb, int m, int n, int k, const typename Scal
                       int64_t batch, void* stream)
 {
     GemmArgs<T> a{};
-    a.Aarr = static_cast<const T* const*>(Aarr);
-    a.Barr = static_cast<const T* const*>(Barr);
+    a.Aarr = static_cast<const void* const*>(Aarr);
+    a.Barr = static_cast<const void* const*>(Barr);
     a.Carr = static_cast<T* const*>(const_cast<void*>(Carr));
     static const Pos pos = {6, 7, 8, 9, 10, 11, 12, 13, 14};
-    return run<T>(ta, tb, m, n, k, alpha, Aarr, lda, Barr, ldb, beta, Carr, ldc, batch, pos, a, true,
-                  stream, nullptr);
+    bool launch = false;
+    const sbg_status_t st = prepare<T>(ta, tb, m, n, k, alpha, Aarr, lda, Barr, ldb, beta, Carr, ldc, batch, pos,
+                                       a, launch, nullptr);
+    if (st != SBG_OK || !launch) return st;
+    return launch_plain<T>(a, true, stream);
 }
+
+
+// Common argument checks of the variable-size forms.  Positions: 1 transa,
+// 2 transb, 3 d_m, 4 d_n, 5 d_k, 6 max_m, 7 max_n, 8 max_k, 9 alpha, 10 Aarray,
+// 11 d_lda, then `extra` (1 for the scaleA of the _ex form), B..., beta, C...,
+// batch, workspace, workspace_bytes.
+struct VbPos { int alpha, A, lda, scaleA, B, ldb, scaleB, beta, C, ldc, batch, ws, wsb; };
+
+template <typename T>
+sbg_status_t vb_run(char transa, char transb, const int* dm, const int* dn, const int* dk, int max_m, int max_n,
+                    int max_k, const void* alpha, const void* Aarr, const int* dlda, const float* scaleA,
+                    const void* Barr, const int* dldb, const float* scaleB, const void* beta, const void* Carr,
+                    const int* dldc, int64_t batch, void* ws, size_t ws_bytes, const VbPos& pos,
+                    GemmArgs<T>& args, bool& launch, bool scales_required)
+{
+    launch = false;
+    tl_last_invalid = 0;
+    const Op oa = decode_op(transa), ob = decode_op(transb);
+    if (oa == OP_BAD) return reject(1);
+    if (ob == OP_BAD) return reject(2);
+    const bool nonempty_b = batch > 0;
+    if (nonempty_b && !dm) return reject(3);
+    if (nonempty_b && !dn) return reject(4);
+    if (nonempty_b && !dk) return reject(5);
+    if (max_m < 0) return reject(6);
+    if (max_n < 0) return reject(7);
+    if (max_k < 0) return reject(8);
+    if (!alpha) return reject(pos.alpha);
+    const bool host = tl_scalar_mode == SBG_SCALAR_HOST;
+    T al{}, be{};
+    if (host) al = Scal<T>::get(static_cast<const typename Scal<T>::api_t*>(alpha));
+    const bool nonempty = nonempty_b && max_m > 0 && max_n > 0;
+    const bool need_ab = nonempty && (!host || (!Scal<T>::zero(al) && max_k > 0));
+    if (need_ab && !Aarr) return reject(pos.A);
+    if (nonempty && !dlda) return reject(pos.lda);
+    if (pos.scaleA && ((scaleA == nullptr) != (scaleB == nullptr) || (scales_required && need_ab && !scaleA)))
+        return reject(pos.scaleA);
+    if (need_ab && !Barr) return reject(pos.B);
+    if (nonempty && !dldb) return reject(pos.ldb);
+    if (pos.scaleB && scales_required && need_ab && !scaleB) return reject(pos.scaleB);
+    if (!beta) return reject(pos.beta);
+    if (nonempty && !Carr) return reject(pos.C);
+    if (nonempty && !dldc) return reject(pos.ldc);
+    if (batch < 0 || batch > 0x7FFFFFFF) return reject(pos.batch);
+    if (nonempty && !ws) return reject(pos.ws);
+    if (max_m > 16 || max_n > 16 || max_k > 16) return SBG_NOT_SUPPORTED;
+    if (!nonempty) return SBG_OK;
+    if (ws_bytes < vb_workspace_bytes(batch)) return SBG_WORKSPACE_TOO_SMALL;
+    if (host) {
+        be = Scal<T>::get(static_cast<const typename Scal<T>::api_t*>(beta));
+        if ((Scal<T>::zero(al) || max_k == 0) && Scal<T>::one(be)) return SBG_OK;
+    }
+    args.dm = dm;
+    args.dn = dn;
+    args.dk = dk;
+    args.dlda = dlda;
+    args.dldb = dldb;
+    args.dldc = dldc;
+    args.max_m = max_m;
+    args.max_n = max_n;
+    args.max_k = max_k;
+    args.ws = static_cast<int*>(ws);
+    args.Aarr = static_cast<const void* const*>(Aarr);
+    args.Barr = static_cast<const void* const*>(Barr);
+    args.Carr = static_cast<T* const*>(const_cast<void*>(Carr));
+    args.scaleA = scaleA;
+    args.scaleB = scaleB;
+    args.a_trans = transposes(oa);
+    args.b_trans = transposes(ob);
+    args.a_conj = conjugates(oa) ? -1.f : 1.f;
+    args.b_conj = conjugates(ob) ? -1.f : 1.f;
+    args.batch = batch;
+    if (host) {
+        args.alpha = al;
+        args.beta = be;
+        args.alpha_dev = nullptr;
+        args.beta_dev = nullptr;
+    } else {
+        args.alpha_dev = static_cast<const T*>(alpha);
+        args.beta_dev = static_cast<const T*>(beta);
+    }
+    launch = true;
+    return SBG_OK;
+}
+
+template <typename T>
+sbg_status_t vbatched(char ta, char tb, const int* dm, const int* dn, const int* dk, int max_m, int max_n, int max_k,
+                      const void* alpha, const void* Aarr, const int* dlda, const void* Barr, const int* dldb,
+                      const void* beta, const void* Carr, const int* dldc, int64_t batch, void* ws,
+                      size_t ws_bytes, void* stream)
+{
+    GemmArgs<T> a{};
+    static const VbPos pos = {9, 10, 11, 0, 12, 13, 0, 14, 15, 16, 17, 18, 19};
+    bool launch = false;
+    sbg_status_t st = vb_run<T>(ta, tb, dm, dn, dk, max_m, max_n, max_k, alpha, Aarr, dlda, nullptr, Barr, dldb,
+                                nullptr, beta, Carr, dldc, batch, ws, ws_bytes, pos, a, launch, false);
+    if (st != SBG_OK || !launch) return st;
+    hipError_t e = launch_vbatched<T>(a, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+bool ab_type_ok(int t) { return t >= 0 && t <= 3; }
 
 }  // namespace
 }  // namespace sbg
@@ -280,6 +398,149 @@ sbg_status_t sbg_zgemm_batched(char ta, char tb, int m, int n, int k, const sbg_
     sbg_cdouble* const* C, int ldc, int64_t batch, void* stream)
 {
     return pointers<double2>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, stream);
+}
+
+size_t sbg_vbatched_workspace_size(int64_t batch_count)
+{
+    return sbg::vb_workspace_bytes(batch_count);
+}
+
+#define SBG_VB_ENTRY(NAME, T, API_T)                                                                   \
+    sbg_status_t NAME(char ta, char tb, const int* d_m, const int* d_n, const int* d_k, int max_m,    \
+                      int max_n, int max_k, const API_T* alpha, const API_T* const* Aarray,            \
+                      const int* d_lda, const API_T* const* Barray, const int* d_ldb, const API_T* beta, \
+                      API_T* const* Carray, const int* d_ldc, int64_t batch_count, void* workspace,     \
+                      size_t workspace_bytes, void* stream)                                             \
+    {                                                                                                   \
+        return sbg::vbatched<T>(ta, tb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda,      \
+                                Barray, d_ldb, beta, Carray, d_ldc, batch_count, workspace,             \
+                                workspace_bytes, stream);                                               \
+    }
+SBG_VB_ENTRY(sbg_sgemm_vbatched, float, float)
+SBG_VB_ENTRY(sbg_dgemm_vbatched, double, double)
+SBG_VB_ENTRY(sbg_cgemm_vbatched, float2, sbg_cfloat)
+SBG_VB_ENTRY(sbg_zgemm_vbatched, double2, sbg_cdouble)
+#undef SBG_VB_ENTRY
+
+sbg_status_t sbg_gemm_strided_batched_ex(char transa, char transb, int m, int n, int k, const float* alpha,
+    const void* A, int lda, int64_t strideA, const float* scaleA, const void* B, int ldb, int64_t strideB,
+    const float* scaleB, const float* beta, float* C, int ldc, int64_t strideC, int64_t batch_count,
+    sbg_datatype_t ab_type, sbg_compute_mode_t mode, void* stream)
+{
+    // positions: 1 transa 2 transb 3 m 4 n 5 k 6 alpha 7 A 8 lda 9 strideA 10 scaleA 11 B 12 ldb
+    // 13 strideB 14 scaleB 15 beta 16 C 17 ldc 18 strideC 19 batch_count 20 ab_type 21 mode
+    // (the GEMM arguments are checked first, then scales, type and mode)
+    sbg::GemmArgs<float> a{};
+    a.A = A;
+    a.B = B;
+    a.C = C;
+    a.strideA = strideA;
+    a.strideB = strideB;
+    a.strideC = strideC;
+    const int64_t strides[3] = {strideA, strideB, strideC};
+    static const sbg::Pos pos = {6, 7, 8, 11, 12, 15, 16, 17, 19};
+    bool launch = false;
+    const sbg_status_t st = sbg::prepare<float>(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                batch_count, pos, a, launch, strides);
+    if (st != SBG_OK) return st;
+    if ((scaleA == nullptr) != (scaleB == nullptr)) return sbg::reject(scaleA ? 14 : 10);
+    if (ab_type == SBG_R_8F_E4M3 && !scaleA) return sbg::reject(10);
+    if (!sbg::ab_type_ok((int)ab_type)) return sbg::reject(20);
+    if (mode != SBG_MODE_PLAIN && mode != SBG_MODE_BF16X3) return sbg::reject(21);
+    if (mode == SBG_MODE_BF16X3 && ab_type != SBG_R_32F) return sbg::reject(21);
+    if (!launch) return SBG_OK;
+    a.scaleA = scaleA;
+    a.scaleB = scaleB;
+    hipError_t e = sbg::launch_gemm_ex(a, (int)ab_type, (int)mode, 0, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+sbg_status_t sbg_gemm_vbatched_ex(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
+    int max_m, int max_n, int max_k, const float* alpha, const void* const* Aarray, const int* d_lda,
+    const float* scaleA, const void* const* Barray, const int* d_ldb, const float* scaleB, const float* beta,
+    float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type, sbg_compute_mode_t mode,
+    void* workspace, size_t workspace_bytes, void* stream)
+{
+    // positions: 1-8 as sbg_?gemm_vbatched, 9 alpha 10 Aarray 11 d_lda 12 scaleA 13 Barray 14 d_ldb
+    // 15 scaleB 16 beta 17 Carray 18 d_ldc 19 batch_count 20 ab_type 21 mode 22 workspace 23 workspace_bytes
+    sbg::GemmArgs<float> a{};
+    static const sbg::VbPos pos = {9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 22, 23};
+    bool launch = false;
+    sbg_status_t st = sbg::vb_run<float>(transa, transb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda,
+                                         scaleA, Barray, d_ldb, scaleB, beta, Carray, d_ldc, batch_count, workspace,
+                                         workspace_bytes, pos, a, launch, ab_type == SBG_R_8F_E4M3);
+    if (st != SBG_OK) return st;
+    if (!sbg::ab_type_ok((int)ab_type)) return sbg::reject(20);
+    if (mode != SBG_MODE_PLAIN && mode != SBG_MODE_BF16X3) return sbg::reject(21);
+    if (mode == SBG_MODE_BF16X3 && ab_type != SBG_R_32F) return sbg::reject(21);
+    if (!launch) return SBG_OK;
+    hipError_t e = sbg::launch_gemm_ex(a, (int)ab_type, (int)mode, 2, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+sbg_status_t sbg_quantize_e4m3_strided_batched(int rows, int cols, const float* X, int ldx, int64_t strideX,
+    unsigned char* Q, int ldq, int64_t strideQ, float* scales, int64_t batch_count, void* stream)
+{
+    sbg::tl_last_invalid = 0;
+    if (rows < 0) return sbg::reject(1);
+    if (cols < 0) return sbg::reject(2);
+    const bool nonempty = rows > 0 && cols > 0 && batch_count > 0;
+    if (nonempty && !X) return sbg::reject(3);
+    if (ldx < (rows > 1 ? rows : 1)) return sbg::reject(4);
+    if (strideX < 0 || (batch_count > 1 && strideX < (int64_t)ldx * cols && strideX != 0)) return sbg::reject(5);
+    if (nonempty && !Q) return sbg::reject(6);
+    if (ldq < (rows > 1 ? rows : 1)) return sbg::reject(7);
+    if (strideQ < 0 || (batch_count > 1 && strideQ < (int64_t)ldq * cols)) return sbg::reject(8);
+    if (batch_count > 0 && !scales) return sbg::reject(9);
+    if (batch_count < 0) return sbg::reject(10);
+    if (rows > 16 || cols > 16) return SBG_NOT_SUPPORTED;
+    if (batch_count == 0) return SBG_OK;
+    sbg::QuantArgs q{};
+    q.rows = rows;
+    q.cols = cols;
+    q.X = X;
+    q.ldx = ldx;
+    q.strideX = strideX;
+    q.Q = Q;
+    q.ldq = ldq;
+    q.strideQ = strideQ;
+    q.scales = scales;
+    q.batch = batch_count;
+    hipError_t e = sbg::launch_quant_e4m3(q, false, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+sbg_status_t sbg_quantize_e4m3_vbatched(const int* d_rows, const int* d_cols, int max_rows, int max_cols,
+    const float* const* Xarray, const int* d_ldx, unsigned char* const* Qarray, const int* d_ldq, float* scales,
+    int64_t batch_count, void* stream)
+{
+    sbg::tl_last_invalid = 0;
+    const bool nonempty = batch_count > 0;
+    if (nonempty && !d_rows) return sbg::reject(1);
+    if (nonempty && !d_cols) return sbg::reject(2);
+    if (max_rows < 0) return sbg::reject(3);
+    if (max_cols < 0) return sbg::reject(4);
+    if (nonempty && !Xarray) return sbg::reject(5);
+    if (nonempty && !d_ldx) return sbg::reject(6);
+    if (nonempty && !Qarray) return sbg::reject(7);
+    if (nonempty && !d_ldq) return sbg::reject(8);
+    if (nonempty && !scales) return sbg::reject(9);
+    if (batch_count < 0) return sbg::reject(10);
+    if (max_rows > 16 || max_cols > 16) return SBG_NOT_SUPPORTED;
+    if (!nonempty) return SBG_OK;
+    sbg::QuantArgs q{};
+    q.drows = d_rows;
+    q.dcols = d_cols;
+    q.max_rows = max_rows;
+    q.max_cols = max_cols;
+    q.Xarr = Xarray;
+    q.dldx = d_ldx;
+    q.Qarr = Qarray;
+    q.dldq = d_ldq;
+    q.scales = scales;
+    q.batch = batch_count;
+    hipError_t e = sbg::launch_quant_e4m3(q, true, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
 }
 
 int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, int k, int lda,

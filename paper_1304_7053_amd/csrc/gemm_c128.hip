@@ -1,5 +1,5 @@
 // Kernel instances for element type double2 (all size classes, both batch forms).
-#include "gemm_mfma.h"
+#include "gemm_vbatched.h"
 #include "gemm_staged.h"
 
 SBG_INSTANTIATE_GEMM(double2)

@@ -1,0 +1,272 @@
+// Batched small-matrix GEMM on CDNA4 matrix cores (gfx950): strided and
+// pointer-array forms.
+//
+// Computes C_p <- alpha op(A_p) op(B_p) + beta C_p (Sec. 2, Eq. (1)) for
+// m, n, k <= 16.  Design (what differs from the paper's Sec. 7 thread-per-
+// entry and register-blocked shared-memory kernels):
+//
+//  * One wavefront owns a "tile": 16/D independent matrices of size class D
+//    (D = 4, 8 or 16) packed block-diagonally into one 16 x 16 x 16 product.
+//    The 16 x 16 x 4 MFMA (f32 or f64) is applied D/4 times; the off-diagonal
+//    blocks of the product mix two different matrices and are discarded.
+//  * MFMA operand layout: lane L = 16 g + c (g = 0..3, c = 0..15) supplies
+//    op(A)(row c, k-index pi) and op(B)(k-index pi, column c) at step kb,
+//    with pi = (D/4) g + kb, so one lane's k-indices are consecutive.  A lane
+//    therefore reads a row of op(A) and a column of op(B) of matrix c / D
+//    straight from global memory: no LDS staging, no shuffles.  When the
+//    k-index is the fast storage index (op T/C on A, op N/R on B) the lane's
+//    D/4 values are one vector load; otherwise neighbouring lanes read
+//    neighbouring addresses.
+//  * The result registers follow the MFMA's own layout: f32 returns rows
+//    4g..4g+3 of column c (one contiguous run, stored with one vector store),
+//    f64 returns rows g, g+4, g+8, g+12.  A register is kept when its row and
+//    column fall in the same diagonal block.
+//  * Transposition selects one of four kernel variants (which operand has k
+//    as its fast index); conjugation is a sign on the imaginary part (the
+//    paper's functor idea, Sec. 6).
+//  * Complex products use four real MFMAs (re*re, -im*im, re*im, im*re); the
+//    3M method is not used (Sec. 8).
+//  * The a1b0 / axpby distinction of Sec. 6 is a wave-uniform branch: with
+//    beta == 0 C is never loaded, with alpha == 0 A and B are never loaded.
+//  * Narrow inputs (bf16, fp16, fp8-e4m3 with per-matrix scales) are decoded
+//    exactly to binary32 as they are loaded; BF16x3 splits binary32 operands
+//    into bf16 hi + lo on the fly.  Accumulation is binary32.
+//  * Each wave keeps U tiles of loads in flight before it computes; the grid
+//    is persistent, and work-groups are renumbered so that each XCD (dispatch
+//    is round-robin over the 8 XCDs) takes runs of `xcd_chunk` consecutive
+//    tile groups, keeping cache lines shared by neighbouring matrices inside
+//    one L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+
+#include "gemm_tile.h"
+
+namespace sbg {
+
+template <typename T> __device__ __forceinline__ void load_scalars(const GemmArgs<T>& a, T& alpha, T& beta)
+{
+    alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
+    beta = a.beta_dev ? *a.beta_dev : a.beta;
+}
+
+// TI: stored type of A and B; MODE: 0 plain, 1 BF16x3; PTR: pointer-array form.
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
+{
+    using R = typename Tr<T>::R;
+    constexpr int P = 16 / D;
+    const LaneGeom<D, R> L;
+    T alpha, beta;
+    load_scalars(a, alpha, beta);
+    const bool a0 = is_zero(alpha), b0 = is_zero(beta);
+
+    const int64_t W = (int64_t)gridDim.x * 4;
+    const int64_t q = xcd_wave_index(a.xcd_chunk);
+    const int64_t ntiles = (a.batch + P - 1) / P;
+    const int64_t ngroups = (ntiles + U - 1) / U;
+
+    for (int64_t grp = q; grp < ngroups; grp += W) {
+        LaneMat<T, TI> mats[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t p = ((grp * U + u) * P) + L.sel;
+            LaneMat<T, TI>& mt = mats[u];
+            mt.valid = p < a.batch;
+            mt.m = a.m;
+            mt.n = a.n;
+            mt.k = a.k;
+            mt.lda = a.lda;
+            mt.ldb = a.ldb;
+            mt.ldc = a.ldc;
+            mt.A = nullptr;
+            mt.B = nullptr;
+            mt.C = nullptr;
+            mt.scale = 1.0f;
+            if (mt.valid) {
+                if (PTR) {
+                    if (!a0) {
+                        mt.A = static_cast<const TI*>(a.Aarr[p]);
+                        mt.B = static_cast<const TI*>(a.Barr[p]);
+                    }
+                    mt.C = a.Carr[p];
+                } else {
+                    mt.A = static_cast<const TI*>(a.A) + p * a.strideA;
+                    mt.B = static_cast<const TI*>(a.B) + p * a.strideB;
+                    mt.C = a.C + p * a.strideC;
+                }
+                if (a.scaleA) mt.scale = a.scaleA[p] * a.scaleB[p];
+            }
+        }
+        tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
+    }
+}
+
+// Work-groups that fit on one CU at once (registers and LDS), cached per kernel.
+template <typename K>
+inline int resident_per_cu(K kernel)
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+        cached = nb;
+    }
+    return cached;
+}
+
+// Persistent grid for `units` independent wave-sized work units: at most the
+// resident work-groups (capped by the tuning knob), a multiple of 8 so the
+// XCD renumbering is exact; sets the XCD run length to a divisor of the
+// waves per XCD.
+template <typename T, typename K>
+inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
+{
+    const Tuning& tu = tuning();
+    int per_cu = resident_per_cu(kernel);
+    if (per_cu > tu.wg_per_cu) per_cu = tu.wg_per_cu;
+    const int64_t wg_needed = (units + 3) / 4;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    int64_t grid = wg_needed < cap ? wg_needed : cap;
+    if (grid < 1) grid = 1;
+    grid = ((grid + 7) / 8) * 8;
+    const int64_t wx = grid / 8 * 4;   // waves per XCD
+    int64_t s = tu.xcd_chunk > 0 ? tu.xcd_chunk : 1;
+    if (s > wx) s = wx;
+    while (wx % s) --s;
+    a.xcd_chunk = s;
+    return grid;
+}
+
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT, bool PTR>
+hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
+{
+    constexpr int U = Unroll<T, D>::value;
+    constexpr int P = 16 / D;
+    auto kern = gemm_mfma_kernel<T, TI, MODE, D, U, ACONT, BCONT, PTR>;
+    const int64_t tiles = (a.batch + P - 1) / P;
+    const int64_t groups = (tiles + U - 1) / U;
+    const int64_t grid = persistent_grid(kern, groups, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int D, bool ACONT, bool BCONT>
+hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream);
+template <typename T>
+int staged_run_length(int m, int n, int k, int64_t batch, int min_waves);
+
+template <typename T, typename TI, int MODE, int D, bool PTR>
+hipError_t launch_ops(const GemmArgs<T>& a, hipStream_t stream)
+{
+    const bool at = a.a_trans, bn = !a.b_trans;
+    if (at) {
+        if (bn) return launch_variant<T, TI, MODE, D, true, true, PTR>(a, stream);
+        return launch_variant<T, TI, MODE, D, true, false, PTR>(a, stream);
+    }
+    if (bn) return launch_variant<T, TI, MODE, D, false, true, PTR>(a, stream);
+    return launch_variant<T, TI, MODE, D, false, false, PTR>(a, stream);
+}
+
+__host__ __device__ inline int size_class(int m, int n, int k)
+{
+    int mx = m > n ? m : n;
+    mx = mx > k ? mx : k;
+    return mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
+}
+
+// Packed layout: minimal leading dimensions and strides (lda, ldb are the
+// stored row counts, which depend on the ops).
+template <typename T>
+inline bool is_packed(const GemmArgs<T>& a)
+{
+    const int64_t ra = a.a_trans ? a.k : a.m, ca = a.a_trans ? a.m : a.k;
+    const int64_t rb = a.b_trans ? a.n : a.k, cb = a.b_trans ? a.k : a.n;
+    return a.k >= 1 && a.lda == ra && a.ldb == rb && a.ldc == a.m && a.strideA == ra * ca &&
+           a.strideB == rb * cb && a.strideC == (int64_t)a.m * a.n;
+}
+
+template <typename T, typename TI, int MODE>
+hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
+{
+    const int D = size_class(a.m, a.n, a.k);
+    if (pointer_form) {
+        if (D == 4) return launch_ops<T, TI, MODE, 4, true>(a, stream);
+        if (D == 8) return launch_ops<T, TI, MODE, 8, true>(a, stream);
+        return launch_ops<T, TI, MODE, 16, true>(a, stream);
+    }
+    if (D == 4) return launch_ops<T, TI, MODE, 4, false>(a, stream);
+    if (D == 8) return launch_ops<T, TI, MODE, 8, false>(a, stream);
+    return launch_ops<T, TI, MODE, 16, false>(a, stream);
+}
+
+// Plain S/D/C/Z: the LDS-staged kernel for packed batches when enabled,
+// otherwise the direct kernel.
+template <typename T>
+hipError_t launch_gemm_impl(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
+{
+    a.G = 0;
+    if (!pointer_form && tuning().staged && is_packed(a))
+        a.G = staged_run_length<T>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
+    if (a.G > 0) {
+        const int D = size_class(a.m, a.n, a.k);
+        const bool at = a.a_trans, bn = !a.b_trans;
+#define SBG_STAGED_OPS(DD)                                                                   \
+    if (D == DD) {                                                                           \
+        if (at) return bn ? launch_staged<T, DD, true, true>(a, stream)                      \
+                          : launch_staged<T, DD, true, false>(a, stream);                    \
+        return bn ? launch_staged<T, DD, false, true>(a, stream)                             \
+                  : launch_staged<T, DD, false, false>(a, stream);                           \
+    }
+        SBG_STAGED_OPS(4)
+        SBG_STAGED_OPS(8)
+        SBG_STAGED_OPS(16)
+#undef SBG_STAGED_OPS
+    }
+    return launch_direct<T, T, 0>(a, pointer_form, stream);
+}
+
+template <typename T> struct TypeName;
+template <> struct TypeName<float> { static constexpr const char* s = "float"; };
+template <> struct TypeName<double> { static constexpr const char* s = "double"; };
+template <> struct TypeName<float2> { static constexpr const char* s = "HIP_vector_type<float, 2u>"; };
+template <> struct TypeName<double2> { static constexpr const char* s = "HIP_vector_type<double, 2u>"; };
+
+// The kernel symbol (as profilers demangle it) a plain launch with these
+// arguments uses, written into buf.
+template <typename T>
+int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
+{
+    const auto tf = [](bool b) { return b ? "true" : "false"; };
+    const int D = size_class(a.m, a.n, a.k);
+    if (!pointer_form && tuning().staged && is_packed(a))
+        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %d, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
+    const int U = D == 4 ? Unroll<T, 4>::value : (D == 8 ? Unroll<T, 8>::value : Unroll<T, 16>::value);
+    return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
+                    TypeName<T>::s, TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form),
+                    TypeName<T>::s);
+}
+
+}  // namespace sbg
+
+#define SBG_INSTANTIATE_GEMM(T)                                                      \
+    namespace sbg {                                                                  \
+    template <>                                                                      \
+    hipError_t launch_gemm<T>(const GemmArgs<T>& a, bool pointer_form, hipStream_t s) \
+    {                                                                                \
+        return launch_gemm_impl<T>(a, pointer_form, s);                              \
+    }                                                                                \
+    template <>                                                                      \
+    int describe_gemm<T>(const GemmArgs<T>& a, bool pointer_form, char* buf, int len) \
+    {                                                                                \
+        return describe_gemm_impl<T>(a, pointer_form, buf, len);                     \
+    }                                                                                \
+    template <>                                                                      \
+    hipError_t launch_vbatched<T>(const GemmArgs<T>& a, hipStream_t s)               \
+    {                                                                                \
+        return launch_vbatched_t<T, T, 0>(a, s);                                     \
+    }                                                                                \
+    }

@@ -20,7 +20,7 @@
 // owns its LDS slice: no work-group barriers, only wave-level ordering.
 #pragma once
 
-#include "gemm_mfma.h"
+#include "gemm_direct.h"
 
 namespace sbg {
 
@@ -87,10 +87,7 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
     }
 
     const int64_t W = (int64_t)gridDim.x * 4;
-    const int64_t local = (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
-    const int64_t xcd = blockIdx.x & 7;
-    const int64_t S = a.xcd_chunk;
-    const int64_t q0 = ((local / S) * 8 + xcd) * S + (local % S);
+    const int64_t q0 = xcd_wave_index(a.xcd_chunk);
     const int64_t nsteps = (a.batch + G - 1) / G;
 
     // One run = G consecutive matrices; its spans and their chunk counts.
@@ -105,8 +102,8 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
         const int64_t p0 = step * G;
         r.cnt = (int)((a.batch - p0) < G ? (a.batch - p0) : G);
         if (r.cnt < 0) r.cnt = 0;
-        r.gA = reinterpret_cast<const unsigned char*>(a.A + p0 * eA);
-        r.gB = reinterpret_cast<const unsigned char*>(a.B + p0 * eB);
+        r.gA = reinterpret_cast<const unsigned char*>(static_cast<const T*>(a.A) + p0 * eA);
+        r.gB = reinterpret_cast<const unsigned char*>(static_cast<const T*>(a.B) + p0 * eB);
         r.gC = reinterpret_cast<unsigned char*>(a.C + p0 * eC);
         r.bytesA = a0 ? 0 : r.cnt * eA * ESZ;
         r.bytesB = a0 ? 0 : r.cnt * eB * ESZ;

@@ -1,0 +1,345 @@
+// Building blocks shared by the batched-GEMM kernels (gfx950): element types,
+// the 16x16x4 MFMA wrappers with their result layouts, narrow-type decoding,
+// the BF16x3 split, and the tile routine that multiplies 16/D packed small
+// matrices held by one wavefront (see gemm_direct.h for the design notes).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "sbg_internal.h"
+
+namespace sbg {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---- storage types of the narrow input formats ----------------------------
+struct bf16_t { unsigned short v; };   // bfloat16: upper half of a binary32
+struct f16_t { unsigned short v; };    // IEEE binary16
+struct e4m3_t { unsigned char v; };    // OCP 8-bit float E4M3 ("fn": no inf, max 448)
+
+template <typename T> struct Tr;
+template <> struct Tr<float>   { using R = float;  static constexpr bool cplx = false; };
+template <> struct Tr<double>  { using R = double; static constexpr bool cplx = false; };
+template <> struct Tr<float2>  { using R = float;  static constexpr bool cplx = true; };
+template <> struct Tr<double2> { using R = double; static constexpr bool cplx = true; };
+
+// 16x16x4 MFMA per real type, with the row held by result register r of lane
+// group g (the column is always the lane index mod 16).
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+    using acc_t = f32x4;
+    static constexpr bool rows_contig = true;
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+    static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    using acc_t = f64x4;
+    static constexpr bool rows_contig = false;
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * r + g; }
+    static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename T> __device__ __forceinline__ typename Tr<T>::R re_of(const T& v);
+template <typename T> __device__ __forceinline__ typename Tr<T>::R im_of(const T& v);
+template <> __device__ __forceinline__ float re_of<float>(const float& v) { return v; }
+template <> __device__ __forceinline__ double re_of<double>(const double& v) { return v; }
+template <> __device__ __forceinline__ float re_of<float2>(const float2& v) { return v.x; }
+template <> __device__ __forceinline__ double re_of<double2>(const double2& v) { return v.x; }
+template <> __device__ __forceinline__ float im_of<float>(const float&) { return 0.f; }
+template <> __device__ __forceinline__ double im_of<double>(const double&) { return 0.0; }
+template <> __device__ __forceinline__ float im_of<float2>(const float2& v) { return v.y; }
+template <> __device__ __forceinline__ double im_of<double2>(const double2& v) { return v.y; }
+
+template <typename T> __device__ __forceinline__ T make_val(typename Tr<T>::R re, typename Tr<T>::R im);
+template <> __device__ __forceinline__ float make_val<float>(float re, float) { return re; }
+template <> __device__ __forceinline__ double make_val<double>(double re, double) { return re; }
+template <> __device__ __forceinline__ float2 make_val<float2>(float re, float im) { return make_float2(re, im); }
+template <> __device__ __forceinline__ double2 make_val<double2>(double re, double im) { return make_double2(re, im); }
+
+template <typename T>
+__device__ __forceinline__ bool is_zero(const T& v) {
+    return re_of<T>(v) == 0 && im_of<T>(v) == 0;
+}
+
+// ---- decoding of stored input elements into the compute type -------------
+// bfloat16 -> binary32: the 16 stored bits are the high half.
+__device__ __forceinline__ float dec(bf16_t x) { return __uint_as_float(((unsigned)x.v) << 16); }
+// binary16 -> binary32 (exact; hardware conversion).
+__device__ __forceinline__ float dec(f16_t x) {
+    _Float16 h;
+    __builtin_memcpy(&h, &x.v, 2);
+    return (float)h;
+}
+// OCP E4M3 -> binary32, exact: sign, 4-bit exponent (bias 7), 3-bit fraction;
+// exponent 0 is subnormal (fraction * 2^-9); S.1111.111 is NaN.
+__device__ __forceinline__ float dec(e4m3_t x) {
+    const unsigned b = x.v;
+    const unsigned s = (b & 0x80u) << 24;
+    const unsigned e = (b >> 3) & 0xFu;
+    const unsigned f = b & 0x7u;
+    float v;
+    if (e == 0xFu && f == 0x7u)
+        v = __uint_as_float(0x7FC00000u);
+    else if (e == 0)
+        v = (float)f * 0x1p-9f;
+    else
+        v = __uint_as_float(((e + 120u) << 23) | (f << 20));
+    return __uint_as_float(__float_as_uint(v) | s);
+}
+__device__ __forceinline__ float dec(float x) { return x; }
+__device__ __forceinline__ double dec(double x) { return x; }
+__device__ __forceinline__ float2 dec(float2 x) { return x; }
+__device__ __forceinline__ double2 dec(double2 x) { return x; }
+
+// Round a binary32 value to the nearest bfloat16 (ties to even), returned as a
+// binary32 holding that bfloat16 value.  Finite inputs only.
+__device__ __forceinline__ float round_bf16(float x) {
+    const unsigned u = __float_as_uint(x);
+    const unsigned bias = 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float((u + bias) & 0xFFFF0000u);
+}
+
+// Read CNT consecutive elements starting at p as one (element-aligned) access.
+template <typename X, int CNT>
+__device__ __forceinline__ void vload(X (&v)[CNT], const X* p) {
+    __builtin_memcpy(v, p, sizeof(X) * CNT);
+}
+template <typename X, int CNT>
+__device__ __forceinline__ void vstore(X* p, const X (&v)[CNT]) {
+    __builtin_memcpy(p, v, sizeof(X) * CNT);
+}
+
+// Epilogue of one entry: alpha * acc + beta * c (real or complex), with the
+// special cases alpha == 0 (acc unused) and beta == 0 (c unused).
+template <typename T>
+__device__ __forceinline__ T axpby(typename Tr<T>::R ar, typename Tr<T>::R ai, typename Tr<T>::R br,
+                                   typename Tr<T>::R bi, bool a0, bool b0, typename Tr<T>::R accr,
+                                   typename Tr<T>::R acci, const T& c)
+{
+    using R = typename Tr<T>::R;
+    const R cr = re_of<T>(c), ci = im_of<T>(c);
+    if (!Tr<T>::cplx) {
+        R o;
+        if (a0)
+            o = b0 ? R(0) : br * cr;
+        else if (b0)
+            o = ar * accr;
+        else
+            o = __builtin_fma(ar, accr, br * cr);
+        return make_val<T>(o, R(0));
+    }
+    R tr = 0, ti = 0;
+    if (!b0) {
+        tr = __builtin_fma(br, cr, -(bi * ci));
+        ti = __builtin_fma(br, ci, bi * cr);
+    }
+    if (!a0) {
+        tr = __builtin_fma(ar, accr, __builtin_fma(-ai, acci, tr));
+        ti = __builtin_fma(ar, acci, __builtin_fma(ai, accr, ti));
+    }
+    return make_val<T>(tr, ti);
+}
+
+// One lane's view of the matrix it serves in a tile.
+template <typename T, typename TI>
+struct LaneMat {
+    const TI* A;
+    const TI* B;
+    T* C;
+    int m, n, k;
+    int64_t lda, ldb, ldc;
+    float scale;   // sA * sB for scaled narrow inputs, 1 otherwise
+    bool valid;
+};
+
+// Per-lane constants of the packed tile layout.
+template <int D, typename R>
+struct LaneGeom {
+    int g, c, sel, ij, kk0;
+    bool keep[4];
+    int orow[4];
+    __device__ __forceinline__ LaneGeom() {
+        const int lane = threadIdx.x & 63;
+        g = lane >> 4;
+        c = lane & 15;
+        sel = c / D;
+        ij = c % D;
+        kk0 = (D / 4) * g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int Rr = Mfma<R>::row(g, r);
+            keep[r] = (Rr / D) == sel;
+            orow[r] = Rr % D;
+        }
+    }
+};
+
+struct Scalars {
+    bool a0, b0;
+};
+
+// U tiles of one wavefront: loads of all U tiles first, then the MFMA steps
+// and the epilogues.  mats[u] describes the matrix this lane serves in tile u.
+// MODE 0: plain; MODE 1: BF16x3 (each binary32 operand split into bf16
+// hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT>
+__device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+                                           const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
+                                           float b_conj)
+{
+    using R = typename Tr<T>::R;
+    using M = Mfma<R>;
+    using acc_t = typename M::acc_t;
+    constexpr bool CPLX = Tr<T>::cplx;
+    constexpr int KB = D / 4;
+    const R ar_ = re_of<T>(alpha), ai_ = im_of<T>(alpha);
+    const R br_ = re_of<T>(beta), bi_ = im_of<T>(beta);
+
+    R xa_r[U][KB], xa_i[U][KB], xb_r[U][KB], xb_i[U][KB];
+    T cin[U][4];
+    bool crun[U];
+
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const LaneMat<T, TI>& mt = mats[u];
+        const bool row_ok = L.ij < mt.m;
+        const bool col_ok = L.ij < mt.n;
+        const bool kfull = L.kk0 + KB <= mt.k;
+        TI va[KB], vb[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            va[kb] = TI{};
+            vb[kb] = TI{};
+        }
+        const bool live = mt.valid && !a0;
+        // op(A) row ij, k-indices kk0 .. kk0+KB-1
+        if (live && row_ok) {
+            if (ACONT) {
+                const TI* src = mt.A + L.ij * mt.lda + L.kk0;
+                if (kfull) {
+                    vload<TI, KB>(va, src);
+                } else {
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb)
+                        if (L.kk0 + kb < mt.k) va[kb] = src[kb];
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (L.kk0 + kb < mt.k) va[kb] = mt.A[L.ij + (L.kk0 + kb) * mt.lda];
+            }
+        }
+        // op(B) column ij, k-indices kk0 .. kk0+KB-1
+        if (live && col_ok) {
+            if (BCONT) {
+                const TI* src = mt.B + L.ij * mt.ldb + L.kk0;
+                if (kfull) {
+                    vload<TI, KB>(vb, src);
+                } else {
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb)
+                        if (L.kk0 + kb < mt.k) vb[kb] = src[kb];
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (L.kk0 + kb < mt.k) vb[kb] = mt.B[L.ij + (L.kk0 + kb) * mt.ldb];
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            // masked entries stay exact zeros (never a NaN from memory)
+            const bool oka = live && row_ok && (L.kk0 + kb) < mt.k;
+            const bool okb = live && col_ok && (L.kk0 + kb) < mt.k;
+            const T da = oka ? dec(va[kb]) : make_val<T>(R(0), R(0));
+            const T db = okb ? dec(vb[kb]) : make_val<T>(R(0), R(0));
+            xa_r[u][kb] = re_of<T>(da);
+            xb_r[u][kb] = re_of<T>(db);
+            xa_i[u][kb] = CPLX ? im_of<T>(da) * (R)a_conj : R(0);
+            xb_i[u][kb] = CPLX ? im_of<T>(db) * (R)b_conj : R(0);
+        }
+        // C input (only when beta != 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cin[u][r] = make_val<T>(R(0), R(0));
+        crun[u] = M::rows_contig && L.keep[0] && col_ok && (L.orow[0] + 3) < mt.m;
+        if (!b0 && mt.valid && col_ok) {
+            const T* cb = mt.C + L.ij * mt.ldc;
+            if (crun[u]) {
+                vload<T, 4>(cin[u], cb + L.orow[0]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (L.keep[r] && L.orow[r] < mt.m) cin[u][r] = cb[L.orow[r]];
+            }
+        }
+    }
+
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const LaneMat<T, TI>& mt = mats[u];
+        acc_t acc_r = {0, 0, 0, 0};
+        acc_t acc_i = {0, 0, 0, 0};
+        if (!a0) {
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                if (MODE == 1) {
+                    const R ah = (R)round_bf16((float)xa_r[u][kb]);
+                    const R al = (R)round_bf16((float)(xa_r[u][kb] - ah));
+                    const R bh = (R)round_bf16((float)xb_r[u][kb]);
+                    const R bl = (R)round_bf16((float)(xb_r[u][kb] - bh));
+                    acc_r = M::run(ah, bh, acc_r);
+                    acc_r = M::run(ah, bl, acc_r);
+                    acc_r = M::run(al, bh, acc_r);
+                } else {
+                    acc_r = M::run(xa_r[u][kb], xb_r[u][kb], acc_r);
+                    if (CPLX) {
+                        acc_r = M::run(-xa_i[u][kb], xb_i[u][kb], acc_r);
+                        acc_i = M::run(xa_r[u][kb], xb_i[u][kb], acc_i);
+                        acc_i = M::run(xa_i[u][kb], xb_r[u][kb], acc_i);
+                    }
+                }
+            }
+        }
+        const bool col_ok = L.ij < mt.n;
+        if (!(mt.valid && col_ok)) continue;
+        // scaled narrow inputs: alpha * sA * sB applied as (alpha sA sB) * acc
+        R ar = ar_, ai = ai_;
+        if (!CPLX && mt.scale != 1.0f) ar = ar_ * (R)mt.scale;
+        T out[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            out[r] = axpby<T>(ar, ai, br_, bi_, a0, b0, acc_r[r], acc_i[r], cin[u][r]);
+        T* cb = mt.C + L.ij * mt.ldc;
+        if (crun[u]) {
+            vstore<T, 4>(cb + L.orow[0], out);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (L.keep[r] && L.orow[r] < mt.m) cb[L.orow[r]] = out[r];
+        }
+    }
+}
+
+// Tiles per wave per step: keep roughly 3-6 KB of operand loads in flight per
+// wave whatever the element size and size class.
+template <typename T, int D> struct Unroll {
+    static constexpr int per_tile = 3 * 16 * D * (int)sizeof(T);   // A, B, C of the packed tile
+    static constexpr int value = per_tile >= 6144 ? 1 : (per_tile >= 3072 ? 2 : 4);
+};
+
+// XCD-aware position of this wave in a persistent grid (gridDim.x % 8 == 0):
+// each XCD takes runs of `chunk` consecutive work units.
+__device__ __forceinline__ int64_t xcd_wave_index(int64_t chunk)
+{
+    const int64_t local = (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
+    const int64_t xcd = blockIdx.x & 7;
+    return ((local / chunk) * 8 + xcd) * chunk + (local % chunk);
+}
+
+}  // namespace sbg

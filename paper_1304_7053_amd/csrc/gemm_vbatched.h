@@ -1,0 +1,134 @@
+// Variable-size batched GEMM: every matrix p has its own (m_p, n_p, k_p) and
+// leading dimensions, all <= 16, in one call.
+//
+// The paper handles unequal sizes by grouping the matrices into sets of
+// identical size and calling the uniform routine per set (Sec. 1).  Here the
+// grouping happens on the device and the whole batch is one persistent
+// launch, so the sequence can be captured once in a HIP graph and replayed
+// with no host round trip:
+//   1. zero_kernel    clears the four counters of the caller's workspace
+//                     (a kernel, not a memset node, so graph replays are safe);
+//   2. bin_kernel     classifies every matrix by size class D in {4, 8, 16}
+//                     (max of m, n, k), appends its index to that class's list
+//                     with one atomic per wave and class, and counts matrices
+//                     whose sizes or leading dimensions are invalid (those are
+//                     skipped, C untouched);
+//   3. vbatched_kernel walks the tiles of the three lists (largest class
+//                     first) with the same tile routine as the uniform forms;
+//                     each lane reads its own matrix's sizes, so one tile may
+//                     pack matrices of different shapes within a class.
+// Workspace (int32 words): [0..2] class counts, [3] rejected matrices,
+// [16 .. 16 + 3 N) the three index lists of capacity N each.
+#pragma once
+
+#include "gemm_direct.h"
+
+namespace sbg {
+
+constexpr int VB_HEADER = 16;
+
+inline size_t vbatched_workspace_bytes(int64_t batch)
+{
+    return (size_t)(VB_HEADER + 3 * (batch > 0 ? batch : 0)) * sizeof(int);
+}
+
+__global__ void vb_zero_kernel(int* ws);
+__global__ __launch_bounds__(256) void vb_bin_kernel(const int* dm, const int* dn, const int* dk, const int* dlda,
+                                                     const int* dldb, const int* dldc, int max_m, int max_n,
+                                                     int max_k, bool a_trans, bool b_trans, int64_t batch,
+                                                     int* ws);
+
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
+__device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, int count, const int* list,
+                                           const T& alpha, const T& beta, bool a0, bool b0)
+{
+    using R = typename Tr<T>::R;
+    constexpr int P = 16 / D;
+    constexpr int U = Unroll<T, D>::value;
+    const LaneGeom<D, R> L;
+    LaneMat<T, TI> mats[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t li = (grp * U + u) * P + L.sel;
+        LaneMat<T, TI>& mt = mats[u];
+        mt.valid = li < count;
+        mt.m = mt.n = mt.k = 0;
+        mt.lda = mt.ldb = mt.ldc = 1;
+        mt.A = nullptr;
+        mt.B = nullptr;
+        mt.C = nullptr;
+        mt.scale = 1.0f;
+        if (mt.valid) {
+            const int p = list[li];
+            mt.m = a.dm[p];
+            mt.n = a.dn[p];
+            mt.k = a.dk[p];
+            mt.lda = a.dlda[p];
+            mt.ldb = a.dldb[p];
+            mt.ldc = a.dldc[p];
+            if (!a0) {
+                mt.A = static_cast<const TI*>(a.Aarr[p]);
+                mt.B = static_cast<const TI*>(a.Barr[p]);
+            }
+            mt.C = a.Carr[p];
+            if (a.scaleA) mt.scale = a.scaleA[p] * a.scaleB[p];
+        }
+    }
+    tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
+}
+
+template <typename T, typename TI, int MODE, bool ACONT, bool BCONT>
+__global__ __launch_bounds__(256) void gemm_vbatched_kernel(const GemmArgs<T> a)
+{
+    T alpha, beta;
+    load_scalars(a, alpha, beta);
+    const bool a0 = is_zero(alpha), b0 = is_zero(beta);
+    const int c4 = a.ws[0], c8 = a.ws[1], c16 = a.ws[2];
+    const int* l4 = a.ws + VB_HEADER;
+    const int* l8 = l4 + a.batch;
+    const int* l16 = l8 + a.batch;
+    constexpr int U4 = Unroll<T, 4>::value, U8 = Unroll<T, 8>::value, U16 = Unroll<T, 16>::value;
+    const int64_t g16 = (c16 + U16 - 1) / U16;
+    const int64_t g8 = ((c8 + 1) / 2 + U8 - 1) / U8;
+    const int64_t g4 = ((c4 + 3) / 4 + U4 - 1) / U4;
+    const int64_t total = g16 + g8 + g4;
+    const int64_t W = (int64_t)gridDim.x * 4;
+    for (int64_t grp = xcd_wave_index(a.xcd_chunk); grp < total; grp += W) {
+        if (grp < g16)
+            vb_process<T, TI, MODE, 16, ACONT, BCONT>(a, grp, c16, l16, alpha, beta, a0, b0);
+        else if (grp < g16 + g8)
+            vb_process<T, TI, MODE, 8, ACONT, BCONT>(a, grp - g16, c8, l8, alpha, beta, a0, b0);
+        else
+            vb_process<T, TI, MODE, 4, ACONT, BCONT>(a, grp - g16 - g8, c4, l4, alpha, beta, a0, b0);
+    }
+}
+
+template <typename T, typename TI, int MODE, bool ACONT, bool BCONT>
+hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
+    const int64_t nb = (a.batch + 255) / 256;
+    hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(256), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,
+                       a.dldc, a.max_m, a.max_n, a.max_k, a.a_trans, a.b_trans, a.batch, a.ws);
+    auto kern = gemm_vbatched_kernel<T, TI, MODE, ACONT, BCONT>;
+    // the class counts are only known on the device: size the grid for the
+    // case with the most work units (every matrix in the 16 class)
+    const int64_t units = (a.batch + Unroll<T, 16>::value - 1) / Unroll<T, 16>::value;
+    const int64_t grid = persistent_grid(kern, units, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, typename TI, int MODE>
+hipError_t launch_vbatched_t(const GemmArgs<T>& a, hipStream_t stream)
+{
+    const bool at = a.a_trans, bn = !a.b_trans;
+    if (at) {
+        if (bn) return launch_vb_variant<T, TI, MODE, true, true>(a, stream);
+        return launch_vb_variant<T, TI, MODE, true, false>(a, stream);
+    }
+    if (bn) return launch_vb_variant<T, TI, MODE, false, true>(a, stream);
+    return launch_vb_variant<T, TI, MODE, false, false>(a, stream);
+}
+
+}  // namespace sbg

@@ -23,19 +23,30 @@ struct GemmArgs {
     int64_t lda, ldb, ldc;
     bool a_trans, b_trans;
     int64_t strideA, strideB, strideC;
-    const T* A;
-    const T* B;
+    const void* A;                 // stored type of A and B may be narrower than T
+    const void* B;
     T* C;
-    const T* const* Aarr;
-    const T* const* Barr;
+    const void* const* Aarr;
+    const void* const* Barr;
     T* const* Carr;
     T alpha, beta;
     const T* alpha_dev;
     const T* beta_dev;
     float a_conj, b_conj;
+    const float* scaleA;           // per-matrix operand scales (fp8 inputs) or null
+    const float* scaleB;
     int64_t batch;
-    int64_t xcd_chunk;   // consecutive tile groups per XCD run (set by the launcher)
-    int G;               // matrices per wave step of the LDS-staged kernel
+    int64_t xcd_chunk;             // consecutive work units per XCD run (set by the launcher)
+    int G;                         // matrices per wave step of the LDS-staged kernel
+    // variable-size form: per-matrix sizes and leading dimensions, workspace
+    const int* dm;
+    const int* dn;
+    const int* dk;
+    const int* dlda;
+    const int* dldb;
+    const int* dldc;
+    int max_m, max_n, max_k;
+    int* ws;
 };
 
 // Launch-shape knobs: work-groups per CU of the persistent grid, the XCD run
@@ -54,6 +65,37 @@ hipError_t launch_gemm(const GemmArgs<T>& a, bool pointer_form, hipStream_t stre
 
 template <typename T>
 int describe_gemm(const GemmArgs<T>& a, bool pointer_form, char* buf, int len);
+
+// Variable-size form (per-matrix sizes in a.dm .. a.dldc, workspace a.ws of
+// vb_workspace_bytes(batch) bytes).
+template <typename T>
+hipError_t launch_vbatched(const GemmArgs<T>& a, hipStream_t stream);
+size_t vb_workspace_bytes(int64_t batch);
+
+// Mixed precision on binary32 C: ab_type 0 f32, 1 bf16, 2 f16, 3 e4m3;
+// mode 0 plain, 1 BF16x3 (ab_type 0 only); form 0 strided, 1 pointer, 2 var-size.
+hipError_t launch_gemm_ex(const GemmArgs<float>& a, int ab_type, int mode, int form, hipStream_t stream);
+
+// Per-matrix absmax E4M3 quantisation: uniform (rows, cols, X, ldx, strideX,
+// Q, ldq, strideQ) or variable-size (drows .. dldq, max_rows, max_cols) batch.
+struct QuantArgs {
+    int rows, cols;
+    const float* X;
+    int64_t ldx, strideX;
+    unsigned char* Q;
+    int64_t ldq, strideQ;
+    const int* drows;
+    const int* dcols;
+    const float* const* Xarr;
+    unsigned char* const* Qarr;
+    const int* dldx;
+    const int* dldq;
+    int max_rows, max_cols;
+    float* scales;
+    int64_t batch;
+};
+
+hipError_t launch_quant_e4m3(const QuantArgs& q, bool var, hipStream_t stream);
 
 int device_cu_count();
 

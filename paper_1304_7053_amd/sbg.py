@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(HERE, "libsbg.so")
 
 SBG_OK, SBG_INVALID_VALUE, SBG_NOT_SUPPORTED, SBG_HIP_ERROR, SBG_WORKSPACE_TOO_SMALL = range(5)
 SCALAR_HOST, SCALAR_DEVICE = 0, 1
+R_32F, R_16BF, R_16F, R_8F_E4M3 = range(4)
+MODE_PLAIN, MODE_BF16X3 = 0, 1
 
 _PREFIX = {torch.float32: "s", torch.float64: "d", torch.complex64: "c", torch.complex128: "z"}
 _REAL = {torch.float32: ctypes.c_float, torch.float64: ctypes.c_double,
@@ -34,6 +36,9 @@ EXPORTS = [
     "sbg_sgemm_batched", "sbg_dgemm_batched", "sbg_cgemm_batched", "sbg_zgemm_batched",
     "sbg_set_scalar_mode", "sbg_get_scalar_mode", "sbg_last_invalid_arg",
     "sbg_status_string", "sbg_version", "sbg_describe_strided",
+    "sbg_vbatched_workspace_size", "sbg_sgemm_vbatched", "sbg_dgemm_vbatched", "sbg_cgemm_vbatched",
+    "sbg_zgemm_vbatched", "sbg_gemm_strided_batched_ex", "sbg_gemm_vbatched_ex",
+    "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched",
 ]
 
 
@@ -74,6 +79,23 @@ def load():
     lib.sbg_describe_strided.argtypes = [c_char, c_char, c_char, c_int, c_int, c_int, c_int, i64, c_int, i64,
                                          c_int, i64, i64, ctypes.c_char_p, c_int]
     lib.sbg_describe_strided.restype = c_int
+    for p in "sdcz":
+        f = getattr(lib, f"sbg_{p}gemm_vbatched")
+        f.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp,
+                      ctypes.c_size_t, vp]
+        f.restype = c_int
+    lib.sbg_vbatched_workspace_size.argtypes = [i64]
+    lib.sbg_vbatched_workspace_size.restype = ctypes.c_size_t
+    lib.sbg_gemm_strided_batched_ex.argtypes = [c_char, c_char, c_int, c_int, c_int, vp, vp, c_int, i64, vp, vp,
+                                                c_int, i64, vp, vp, vp, c_int, i64, i64, c_int, c_int, vp]
+    lib.sbg_gemm_strided_batched_ex.restype = c_int
+    lib.sbg_gemm_vbatched_ex.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp,
+                                         vp, vp, vp, vp, i64, c_int, c_int, vp, ctypes.c_size_t, vp]
+    lib.sbg_gemm_vbatched_ex.restype = c_int
+    lib.sbg_quantize_e4m3_strided_batched.argtypes = [c_int, c_int, vp, c_int, i64, vp, c_int, i64, vp, i64, vp]
+    lib.sbg_quantize_e4m3_strided_batched.restype = c_int
+    lib.sbg_quantize_e4m3_vbatched.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp, vp, i64, vp]
+    lib.sbg_quantize_e4m3_vbatched.restype = c_int
     _lib = lib
     return lib
 
@@ -147,6 +169,95 @@ def gemm_batched(transa, transb, m, n, k, alpha, Aptrs, lda, Bptrs, ldb, beta, C
            batch, _stream(stream))
     if check:
         _check(st, "gemm_batched")
+    return st
+
+
+def _scalars(alpha, beta, dtype):
+    """(alpha, beta, device_mode) as ctypes pointers: Python numbers go to host
+    buffers, 1-element device tensors are passed as device pointers."""
+    if isinstance(alpha, torch.Tensor):
+        return ctypes.c_void_p(alpha.data_ptr()), ctypes.c_void_p(beta.data_ptr()), True
+    al, be = _scalar_buf(alpha, dtype), _scalar_buf(beta, dtype)
+    return al, be, False
+
+
+def _call_scalars(fn, alpha, beta, dtype, *args):
+    """Call fn(alpha_ptr, beta_ptr) with the scalar mode set for the call."""
+    L = load()
+    al, be, dev = _scalars(alpha, beta, dtype)
+    if dev:
+        L.sbg_set_scalar_mode(SCALAR_DEVICE)
+    try:
+        return fn(ctypes.cast(al, ctypes.c_void_p) if not dev else al,
+                  ctypes.cast(be, ctypes.c_void_p) if not dev else be)
+    finally:
+        if dev:
+            L.sbg_set_scalar_mode(SCALAR_HOST)
+
+
+def vbatched_workspace_size(batch):
+    return int(load().sbg_vbatched_workspace_size(batch))
+
+
+def gemm_vbatched(transa, transb, dm, dn, dk, max_m, max_n, max_k, alpha, Aptrs, dlda, Bptrs, dldb, beta, Cptrs,
+                  dldc, batch, workspace, dtype, stream=None, check=True):
+    """Variable-size form: dm..dldc are int32 device tensors, *ptrs int64
+    device tensors of addresses, workspace a device tensor of at least
+    vbatched_workspace_size(batch) bytes."""
+    L = load()
+    f = getattr(L, f"sbg_{_PREFIX[dtype]}gemm_vbatched")
+    st = _call_scalars(lambda al, be: f(transa.encode(), transb.encode(), _dptr(dm), _dptr(dn), _dptr(dk), max_m,
+                                        max_n, max_k, al, _dptr(Aptrs), _dptr(dlda), _dptr(Bptrs), _dptr(dldb), be,
+                                        _dptr(Cptrs), _dptr(dldc), batch, _dptr(workspace),
+                                        workspace.numel() * workspace.element_size(), _stream(stream)),
+                       alpha, beta, dtype)
+    if check:
+        _check(st, "gemm_vbatched")
+    return st
+
+
+def gemm_strided_ex(transa, transb, m, n, k, alpha, A, lda, strideA, scaleA, B, ldb, strideB, scaleB, beta, C, ldc,
+                    strideC, batch, ab_type, mode=MODE_PLAIN, stream=None, check=True):
+    """Mixed-precision strided form (binary32 C); A and B are device tensors of
+    the stored type (bf16/fp16 tensors, uint8 for e4m3), scales float32 or None."""
+    L = load()
+    st = _call_scalars(lambda al, be: L.sbg_gemm_strided_batched_ex(
+        transa.encode(), transb.encode(), m, n, k, al, _dptr(A), lda, strideA, _dptr(scaleA), _dptr(B), ldb,
+        strideB, _dptr(scaleB), be, _dptr(C), ldc, strideC, batch, ab_type, mode, _stream(stream)),
+        alpha, beta, torch.float32)
+    if check:
+        _check(st, "gemm_strided_ex")
+    return st
+
+
+def gemm_vbatched_ex(transa, transb, dm, dn, dk, max_m, max_n, max_k, alpha, Aptrs, dlda, scaleA, Bptrs, dldb,
+                     scaleB, beta, Cptrs, dldc, batch, ab_type, mode, workspace, stream=None, check=True):
+    L = load()
+    st = _call_scalars(lambda al, be: L.sbg_gemm_vbatched_ex(
+        transa.encode(), transb.encode(), _dptr(dm), _dptr(dn), _dptr(dk), max_m, max_n, max_k, al, _dptr(Aptrs),
+        _dptr(dlda), _dptr(scaleA), _dptr(Bptrs), _dptr(dldb), _dptr(scaleB), be, _dptr(Cptrs), _dptr(dldc), batch,
+        ab_type, mode, _dptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream)),
+        alpha, beta, torch.float32)
+    if check:
+        _check(st, "gemm_vbatched_ex")
+    return st
+
+
+def quantize_e4m3_strided(rows, cols, X, ldx, strideX, Q, ldq, strideQ, scales, batch, stream=None, check=True):
+    st = load().sbg_quantize_e4m3_strided_batched(rows, cols, _dptr(X), ldx, strideX, _dptr(Q), ldq, strideQ,
+                                                  _dptr(scales), batch, _stream(stream))
+    if check:
+        _check(st, "quantize_e4m3_strided")
+    return st
+
+
+def quantize_e4m3_vbatched(drows, dcols, max_rows, max_cols, Xptrs, dldx, Qptrs, dldq, scales, batch, stream=None,
+                           check=True):
+    st = load().sbg_quantize_e4m3_vbatched(_dptr(drows), _dptr(dcols), max_rows, max_cols, _dptr(Xptrs),
+                                           _dptr(dldx), _dptr(Qptrs), _dptr(dldq), _dptr(scales), batch,
+                                           _stream(stream))
+    if check:
+        _check(st, "quantize_e4m3_vbatched")
     return st
 
 

@@ -1,0 +1,225 @@
+"""GPU parity of the precision modes (binary32 accumulation and C): bf16,
+fp16 and fp8-e4m3 inputs (with per-matrix absmax scales produced by the
+library's quantiser) and the BF16x3 split mode.
+
+Kernel-only parity: the oracle evaluates the same stored (decoded, scaled)
+operands exactly, so products of narrow values being exact in binary32 the
+bound is the plain 4 max(k,1) u, u = 2^-24.  BF16x3 accumulates three
+products per k-step: its bound is 4 * 3 max(k,1) u against the oracle's
+split product.  The error of each mode against the binary32-input product
+(the quantisation error) is reported, not pinned."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1304_7053_amd import inputs, sbg
+from gpu_util import VarCase, check_var, from_dev, normalised_error, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+NARROW = {"bf16": (torch.bfloat16, sbg.R_16BF), "f16": (torch.float16, sbg.R_16F)}
+
+
+def strided_inputs(g, ta, tb, m, n, k, batch, dist="uniform"):
+    ra, ca = (m, k) if ta == "N" else (k, m)
+    rb, cb = (k, n) if tb == "N" else (n, k)
+    A = inputs.strided_batch(g, batch, ra, ca, ra, ra * ca, np.float32, dist)
+    B = inputs.strided_batch(g, batch, rb, cb, rb, rb * cb, np.float32, dist)
+    C = inputs.strided_batch(g, batch, m, n, m, m * n, np.float32, dist)
+    return A, B, C, ra, rb
+
+
+def unpack(flat, batch, m, n):
+    return np.swapaxes(flat.reshape(batch, n, m), 1, 2)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+@pytest.mark.parametrize("dist", ["uniform", "logu"])
+def test_half_inputs_strided(gpu_lib, fmt, dist):
+    tdt, code = NARROW[fmt]
+    g = inputs.rng(4, salt=10)
+    for (ta, tb, s) in [("N", "N", 16), ("T", "N", 8), ("N", "T", 5), ("T", "T", 13), ("N", "N", 1)]:
+        batch = 1001
+        A, B, C, ra, rb = strided_inputs(g, ta, tb, s, s, s, batch, dist)
+        dA = torch.from_numpy(A).to("cuda").to(tdt)
+        dB = torch.from_numpy(B).to("cuda").to(tdt)
+        dC = to_dev(C)
+        say(f"{fmt} {dist} {ta}{tb} n={s}")
+        sbg.gemm_strided_ex(ta, tb, s, s, s, 1.5, dA, ra, ra * s, None, dB, rb, rb * s, None, -0.5, dC, s, s * s,
+                            batch, code)
+        torch.cuda.synchronize()
+        Ab = dA.view(torch.int16).cpu().numpy().view(np.uint16)
+        Bb = dB.view(torch.int16).cpu().numpy().view(np.uint16)
+        types = (fmt, fmt, "f32")
+        hi, lo = oracle.gemm_strided(ta, tb, s, s, s, 1.5, Ab, ra, ra * s, Bb, rb, rb * s, -0.5, C, s, s * s,
+                                     batch, ext=True, types=types)
+        bnd = oracle.bound_strided(ta, tb, s, s, s, 1.5, Ab, ra, ra * s, Bb, rb, rb * s, -0.5, C, s, s * s, batch,
+                                   types=types)
+        got = unpack(from_dev(dC), batch, s, s)
+        e = normalised_error(got, hi, lo, bnd)
+        assert np.max(e) <= 4 * max(s, 1) * U32, (fmt, ta, tb, s, np.max(e) / U32)
+        # end-to-end error against the binary32 inputs (reported)
+        h32, l32 = oracle.gemm_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s,
+                                       batch, ext=True)
+        b32 = oracle.bound_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s, batch)
+        say(f"  end-to-end max normalised error vs fp32 inputs: {np.max(normalised_error(got, h32, l32, b32)):.3e}")
+
+
+def test_quantiser_matches_oracle_bitwise(gpu_lib):
+    g = inputs.rng(4, salt=11)
+    for (rows, cols, dist) in [(16, 16, "uniform"), (7, 3, "logu"), (1, 1, "uniform"), (12, 9, "logu")]:
+        batch, ld = 777, rows + 2
+        X = inputs.strided_batch(g, batch, rows, cols, ld, ld * cols + 1, np.float32, dist, fill=np.nan)
+        X[: ld * cols + 1][np.isfinite(X[: ld * cols + 1])] = 0.0        # an all-zero matrix: scale 1
+        dX = to_dev(X)
+        dQ = torch.full((batch * rows * cols + 5,), 0xAB, dtype=torch.uint8, device="cuda")
+        dS = torch.zeros(batch, dtype=torch.float32, device="cuda")
+        say(f"quantise {rows}x{cols} {dist}")
+        sbg.quantize_e4m3_strided(rows, cols, dX, ld, ld * cols + 1, dQ, rows, rows * cols, dS, batch)
+        torch.cuda.synchronize()
+        off = np.arange(batch, dtype=np.int64) * (ld * cols + 1)
+        Q, offQ, S = oracle.quant_e4m3(X, off, rows, cols, ld, batch)
+        assert np.array_equal(from_dev(dS), S)
+        assert np.array_equal(from_dev(dQ)[: batch * rows * cols], Q[: batch * rows * cols])
+        assert np.all(from_dev(dQ)[batch * rows * cols:] == 0xAB)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "logu"])
+def test_fp8_scaled_strided(gpu_lib, dist):
+    g = inputs.rng(4, salt=12)
+    for (ta, tb, s) in [("N", "N", 16), ("T", "N", 8), ("N", "T", 3), ("T", "T", 11)]:
+        batch = 903
+        A, B, C, ra, rb = strided_inputs(g, ta, tb, s, s, s, batch, dist)
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        qA = torch.empty(A.size, dtype=torch.uint8, device="cuda")
+        qB = torch.empty(B.size, dtype=torch.uint8, device="cuda")
+        sA = torch.empty(batch, dtype=torch.float32, device="cuda")
+        sB = torch.empty(batch, dtype=torch.float32, device="cuda")
+        say(f"fp8 {dist} {ta}{tb} n={s}")
+        sbg.quantize_e4m3_strided(ra, s if ta == "N" else s, dA, ra, ra * s, qA, ra, ra * s, sA, batch)
+        sbg.quantize_e4m3_strided(rb, s, dB, rb, rb * s, qB, rb, rb * s, sB, batch)
+        sbg.gemm_strided_ex(ta, tb, s, s, s, 1.5, qA, ra, ra * s, sA, qB, rb, rb * s, sB, -0.5, dC, s, s * s, batch,
+                            sbg.R_8F_E4M3)
+        torch.cuda.synchronize()
+        Qa, Qb = from_dev(qA), from_dev(qB)
+        Sa, Sb = from_dev(sA).astype(np.float64), from_dev(sB).astype(np.float64)
+        types = ("e4m3", "e4m3", "f32")
+        hi, lo = oracle.gemm_strided(ta, tb, s, s, s, 1.5, Qa, ra, ra * s, Qb, rb, rb * s, -0.5, C, s, s * s, batch,
+                                     ext=True, types=types, scaleA=Sa, scaleB=Sb)
+        bnd = oracle.bound_strided(ta, tb, s, s, s, 1.5, Qa, ra, ra * s, Qb, rb, rb * s, -0.5, C, s, s * s, batch,
+                                   types=types, scaleA=Sa, scaleB=Sb)
+        got = unpack(from_dev(dC), batch, s, s)
+        e = normalised_error(got, hi, lo, bnd)
+        assert np.max(e) <= 4 * max(s, 1) * U32, (ta, tb, s, np.max(e) / U32)
+        h32, l32 = oracle.gemm_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s,
+                                       batch, ext=True)
+        b32 = oracle.bound_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s, batch)
+        say(f"  end-to-end max normalised error vs fp32 inputs: {np.max(normalised_error(got, h32, l32, b32)):.3e}")
+
+
+@pytest.mark.parametrize("dist", ["uniform", "logu"])
+def test_bf16x3_strided(gpu_lib, dist):
+    g = inputs.rng(4, salt=13)
+    for (ta, tb, s) in [("N", "N", 16), ("T", "N", 9), ("N", "T", 4), ("T", "T", 16)]:
+        batch = 1003
+        A, B, C, ra, rb = strided_inputs(g, ta, tb, s, s, s, batch, dist)
+        dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+        say(f"bf16x3 {dist} {ta}{tb} n={s}")
+        sbg.gemm_strided_ex(ta, tb, s, s, s, 1.5, dA, ra, ra * s, None, dB, rb, rb * s, None, -0.5, dC, s, s * s,
+                            batch, sbg.R_32F, sbg.MODE_BF16X3)
+        torch.cuda.synchronize()
+        p = np.arange(batch, dtype=np.int64)
+        hi, lo, bnd, _, _, _ = oracle.gemm_split3_general(ta, tb, s, s, s, 1.5, A, p * ra * s, ra, B, p * rb * s,
+                                                          rb, -0.5, C, p * s * s, s, batch)
+        got = unpack(from_dev(dC), batch, s, s)
+        e = normalised_error(got, unpack(hi, batch, s, s), unpack(lo, batch, s, s), unpack(bnd, batch, s, s))
+        assert np.max(e) <= 4 * 3 * max(s, 1) * U32, (ta, tb, s, np.max(e) / U32)
+        h32, l32 = oracle.gemm_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s,
+                                       batch, ext=True)
+        b32 = oracle.bound_strided(ta, tb, s, s, s, 1.5, A, ra, ra * s, B, rb, rb * s, -0.5, C, s, s * s, batch)
+        say(f"  end-to-end max normalised error vs fp32 inputs: {np.max(normalised_error(got, h32, l32, b32)):.3e}")
+
+
+@pytest.mark.parametrize("mode", ["bf16", "f16", "e4m3", "bf16x3", "f32"])
+def test_precision_modes_vbatched(gpu_lib, mode):
+    """The variable-size workload shape in every precision mode: sizes as in
+    the variable-size batch, pointer arrays, device binning."""
+    g = inputs.rng(4, salt=14)
+    dims = inputs.varsize_dims(g, 1500)
+    c = VarCase(np.float32, "N", "N", dims, 1.5, -0.5, g, pad=False)
+    d = c.device()
+    N = c.batch
+    kw = {}
+    Ast, Bst = c.A, c.B
+    if mode in ("bf16", "f16"):
+        tdt, code = NARROW[mode]
+        nA = d["A"].to(tdt)
+        nB = d["B"].to(tdt)
+        pA = torch.tensor(nA.data_ptr() + c.offA * 2, device="cuda")
+        pB = torch.tensor(nB.data_ptr() + c.offB * 2, device="cuda")
+        sA = sB = None
+        cmode = sbg.MODE_PLAIN
+        Ast = nA.view(torch.int16).cpu().numpy().view(np.uint16)
+        Bst = nB.view(torch.int16).cpu().numpy().view(np.uint16)
+        kw = dict(types=(mode, mode, "f32"))
+    elif mode == "e4m3":
+        code, cmode = sbg.R_8F_E4M3, sbg.MODE_PLAIN
+        qA = torch.zeros(c.A.size, dtype=torch.uint8, device="cuda")
+        qB = torch.zeros(c.B.size, dtype=torch.uint8, device="cuda")
+        sA = torch.empty(N, dtype=torch.float32, device="cuda")
+        sB = torch.empty(N, dtype=torch.float32, device="cuda")
+        pA = torch.tensor(qA.data_ptr() + c.offA, device="cuda")
+        pB = torch.tensor(qB.data_ptr() + c.offB, device="cuda")
+        sbg.quantize_e4m3_vbatched(d["m"], d["k"], 16, 16, d["pA"], d["lda"], pA, d["lda"], sA, N)
+        sbg.quantize_e4m3_vbatched(d["k"], d["n"], 16, 16, d["pB"], d["ldb"], pB, d["ldb"], sB, N)
+        torch.cuda.synchronize()
+        Ast, Bst = from_dev(qA), from_dev(qB)
+        kw = dict(types=("e4m3", "e4m3", "f32"), scaleA=from_dev(sA).astype(np.float64),
+                  scaleB=from_dev(sB).astype(np.float64))
+    else:
+        code = sbg.R_32F
+        cmode = sbg.MODE_BF16X3 if mode == "bf16x3" else sbg.MODE_PLAIN
+        pA, pB, sA, sB = d["pA"], d["pB"], None, None
+    say(f"vbatched_ex {mode} N={N}")
+    sbg.gemm_vbatched_ex("N", "N", d["m"], d["n"], d["k"], 16, 16, 16, 1.5, pA, d["lda"], sA, pB, d["ldb"], sB,
+                         -0.5, d["pC"], d["ldc"], N, code, cmode, d["ws"])
+    torch.cuda.synchronize()
+    out = from_dev(d["C"])
+    if mode == "bf16x3":
+        hi, lo, bnd, offO, mm, nn = oracle.gemm_split3_general("N", "N", c.m, c.n, c.k, 1.5, c.A, c.offA, c.lda,
+                                                               c.B, c.offB, c.ldb, -0.5, c.C, c.offC, c.ldc, N)
+        for p in range(N):
+            m, n = int(c.m[p]), int(c.n[p])
+            if m == 0 or n == 0:
+                continue
+            o = int(offO[p])
+            e = normalised_error(c.got(out, p), hi[o:o + m * n].reshape(n, m).T, lo[o:o + m * n].reshape(n, m).T,
+                                 bnd[o:o + m * n].reshape(n, m).T)
+            assert np.max(e) <= 12 * max(int(c.k[p]), 1) * U32, (p, np.max(e) / U32)
+    else:
+        check_var(c, out, label=f"vbatched_ex {mode}", A=Ast, B=Bst, **kw)
+
+
+def test_ex_argument_checks(gpu_lib):
+    """Precision arguments are validated after the GEMM arguments."""
+    L = sbg.load()
+    import ctypes
+    one = (ctypes.c_float * 1)(1.0)
+    a = ctypes.cast(one, ctypes.c_void_p)
+    dev = torch.zeros(64, device="cuda")
+    p = ctypes.c_void_p(dev.data_ptr())
+    # fp8 without scales
+    st = L.sbg_gemm_strided_batched_ex(b"N", b"N", 4, 4, 4, a, p, 4, 16, None, p, 4, 16, None, a, p, 4, 16, 1,
+                                       sbg.R_8F_E4M3, sbg.MODE_PLAIN, None)
+    assert st == sbg.SBG_INVALID_VALUE and sbg.last_invalid_arg() == 10
+    # BF16x3 on bf16 storage
+    st = L.sbg_gemm_strided_batched_ex(b"N", b"N", 4, 4, 4, a, p, 4, 16, None, p, 4, 16, None, a, p, 4, 16, 1,
+                                       sbg.R_16BF, sbg.MODE_BF16X3, None)
+    assert st == sbg.SBG_INVALID_VALUE and sbg.last_invalid_arg() == 21
+    # unknown type
+    st = L.sbg_gemm_strided_batched_ex(b"N", b"N", 4, 4, 4, a, p, 4, 16, None, p, 4, 16, None, a, p, 4, 16, 1,
+                                       9, sbg.MODE_PLAIN, None)
+    assert st == sbg.SBG_INVALID_VALUE and sbg.last_invalid_arg() == 20
+    torch.cuda.synchronize()
