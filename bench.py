@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10000,
                     help="matrices per (dtype, n, op) call timed on the CPU oracle")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary workloads (small batch, complex, variable-size modes, FEM)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, copy 1 GiB once (reference kernel for HBM byte counters)")
     return ap.parse_args()
@@ -177,9 +179,22 @@ def main():
     sizes_out = {k: {"gflops": round(v[0] / v[2] / 1e9, 1), "hbm_frac": round(v[1] / v[2] / HBM_PEAK, 4)}
                  for k, v in per_size.items()}
 
+    # free the sweep's 29 GB before the secondary workloads
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(calls, args.cpu_sample)
+    del calls
+    torch.cuda.empty_cache()
+    secondary = None
+    if not args.no_extras:
+        secondary = {}
+        for name, fn in (("small_batch", sec_small_batch), ("complex", sec_complex_sweep),
+                         ("varsize_precision", sec_varsize_modes), ("fem", sec_fem_chain)):
+            try:
+                secondary[name] = fn(stream)
+            except Exception as e:  # a secondary failure must not hide the primary line
+                secondary[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
@@ -205,10 +220,263 @@ def main():
         "fp32_n16": head,
         "per_size": sizes_out,
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     if calib:
         out["calib_copy"] = calib
     print(json.dumps(out), flush=True)
+
+
+# ---- secondary workloads (reported beside the primary line) ---------------
+
+def _graph(fn, stream):
+    """Capture fn() (library calls on the current stream) in a HIP graph."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        fn()                       # warm-up outside capture
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def _time_replays(g, reps, flush=None):
+    """Median and min seconds of graph replays, the Infinity Cache flushed
+    (a 512 MB write) before each one outside the timed interval."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cur = torch.cuda.current_stream()
+        e0.record(cur)
+        g.replay()
+        e1.record(cur)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], ts[0]
+
+
+def sec_small_batch(stream):
+    """N = 1000 pairs of 8x8x8, NN, alpha = 1, beta = 0 (C not read): launch
+    latency regime.  Median time of an eager call and of a graph replay."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    N, s = 1000, 8
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 1)
+    A = torch.rand(N * s * s, generator=gen, device="cuda") * 2 - 1
+    B = torch.rand(N * s * s, generator=gen, device="cuda") * 2 - 1
+    C = torch.empty(N * s * s, device="cuda")
+    call = lambda: sbg.gemm_strided("N", "N", s, s, s, 1.0, A, s, s * s, B, s, s * s, 0.0, C, s, s * s, N)  # noqa
+    ts = []
+    for _ in range(200):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    ts.sort()
+    g = _graph(call, stream)
+    med_g, _ = _time_replays(g, 200)
+    return {"workload": "N=1000, 8x8x8, NN, alpha=1, beta=0, fp32", "us_per_call_median": round(ts[100], 2),
+            "us_per_graph_replay_median": round(med_g * 1e6, 2),
+            "gflops_per_call": round(2 * s ** 3 * N / (ts[100] * 1e-6) / 1e9, 1)}
+
+
+def sec_complex_sweep(stream):
+    """N = 100,000 complex pairs, n in {4, 8, 12, 16}, all nine op pairs over
+    {N, T, C}, alpha = (1, 0.5), beta = (0.25, -1); GFLOP/s (8 n^3 per
+    matrix) and HBM fraction per (type, n), each call on its own buffers."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    N = 100_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 3)
+    out = {}
+    for tdt, esz, name in ((torch.complex64, 8, "c"), (torch.complex128, 16, "z")):
+        rdt = torch.float32 if tdt == torch.complex64 else torch.float64
+        for n in (4, 8, 12, 16):
+            el = N * n * n
+            bufs = []
+            for _ in range(9):
+                bufs.append([(torch.rand(2 * el, generator=gen, device="cuda", dtype=rdt) * 2 - 1).view(tdt)
+                             for _ in range(3)])
+            ops = [a + b for a in "NTC" for b in "NTC"]
+            for i, op in enumerate(ops):     # warm-up
+                A, B, C = bufs[i]
+                sbg.gemm_strided(op[0], op[1], n, n, n, complex(1, 0.5), A, n, n * n, B, n, n * n,
+                                 complex(0.25, -1), C, n, n * n, N)
+            torch.cuda.synchronize()
+            evs = []
+            for rep in range(3):
+                for i, op in enumerate(ops):
+                    A, B, C = bufs[i]
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    sbg.gemm_strided(op[0], op[1], n, n, n, complex(1, 0.5), A, n, n * n, B, n, n * n,
+                                     complex(0.25, -1), C, n, n * n, N)
+                    e1.record(stream)
+                    evs.append((op, e0, e1))
+            torch.cuda.synchronize()
+            t_op = {}
+            for op, e0, e1 in evs:
+                t_op.setdefault(op, []).append(e0.elapsed_time(e1) / 1e3)
+            tmed = {op: sorted(v)[len(v) // 2] for op, v in t_op.items()}
+            tot = sum(tmed.values())
+            flops = 8.0 * n ** 3 * N * 9
+            byts = 4.0 * n * n * esz * N * 9
+            out[f"{name}{n}"] = {"gflops": round(flops / tot / 1e9, 1), "hbm_frac": round(byts / tot / HBM_PEAK, 4),
+                                 "op_vs_NN": {op: round(tmed["NN"] / t, 3) for op, t in tmed.items()}}
+            del bufs
+            torch.cuda.empty_cache()
+    return out
+
+
+def sec_varsize_modes(stream):
+    """N = 200,000 matrices with m, n, k drawn independently (40% at 8, 30% at
+    16, the rest uniform), pointer arrays, one variable-size call (binning +
+    persistent GEMM) captured in a HIP graph; for each precision mode and
+    both input sets: GFLOP/s, HBM fraction (algorithmic bytes incl. per-matrix
+    pointers, sizes, leading dimensions and scales) and the deviation from the
+    binary32 result of the same call."""
+    import numpy as np
+    import torch
+
+    from paper_1304_7053_amd import inputs, sbg
+    N = 200_000
+    g = inputs.rng(4)
+    m, n, k = inputs.varsize_dims(g, N)
+    m64, n64, k64 = (x.astype(np.int64) for x in (m, n, k))
+    offs = {}
+    for name, cnt in (("A", m64 * k64), ("B", k64 * n64), ("C", m64 * n64)):
+        o = np.zeros(N, dtype=np.int64)
+        o[1:] = np.cumsum(cnt)[:-1]
+        offs[name] = (o, int(cnt.sum()))
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    dm, dn, dk = dev(m), dev(n), dev(k)
+    dlda, dldb, dldc = dev(np.maximum(m, 1)), dev(np.maximum(k, 1)), dev(np.maximum(m, 1))
+    ws = torch.zeros(sbg.vbatched_workspace_size(N) // 4 + 1, dtype=torch.int32, device="cuda")
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+    flops = float(np.sum(2 * m64 * n64 * k64))
+    meta = 24 + 24                          # three pointers, six int32 sizes / leading dimensions
+    res = {"workload": "N=200000 variable m,n,k (40% 8, 30% 16, rest uniform), NN, alpha=1.5, beta=-0.5",
+           "gflop_per_call": round(flops / 1e9, 4)}
+    for dist in ("uniform", "logu"):
+        A32 = dev(inputs.DISTS[dist](g, (offs["A"][1],), np.float32))
+        B32 = dev(inputs.DISTS[dist](g, (offs["B"][1],), np.float32))
+        C0 = dev(inputs.DISTS[dist](g, (offs["C"][1],), np.float32))
+        C = torch.empty_like(C0)
+        pC = torch.tensor(C.data_ptr() + offs["C"][0] * 4, device="cuda")
+        results = {}
+        ref = None
+        for mode in ("f32", "bf16", "f16", "e4m3", "bf16x3"):
+            sA = sB = None
+            qtime = None
+            if mode in ("bf16", "f16"):
+                tdt = torch.bfloat16 if mode == "bf16" else torch.float16
+                Ain, Bin, esz = A32.to(tdt), B32.to(tdt), 2
+                code, cmode = (sbg.R_16BF if mode == "bf16" else sbg.R_16F), sbg.MODE_PLAIN
+            elif mode == "e4m3":
+                Ain = torch.empty(offs["A"][1], dtype=torch.uint8, device="cuda")
+                Bin = torch.empty(offs["B"][1], dtype=torch.uint8, device="cuda")
+                esz, code, cmode = 1, sbg.R_8F_E4M3, sbg.MODE_PLAIN
+                sA = torch.empty(N, device="cuda")
+                sB = torch.empty(N, device="cuda")
+                pA32 = torch.tensor(A32.data_ptr() + offs["A"][0] * 4, device="cuda")
+                pB32 = torch.tensor(B32.data_ptr() + offs["B"][0] * 4, device="cuda")
+                pAq = torch.tensor(Ain.data_ptr() + offs["A"][0], device="cuda")
+                pBq = torch.tensor(Bin.data_ptr() + offs["B"][0], device="cuda")
+
+                def quant():
+                    sbg.quantize_e4m3_vbatched(dm, dk, 16, 16, pA32, dlda, pAq, dlda, sA, N)
+                    sbg.quantize_e4m3_vbatched(dk, dn, 16, 16, pB32, dldb, pBq, dldb, sB, N)
+                qg = _graph(quant, stream)
+                qtime, _ = _time_replays(qg, 5, flush)
+            else:
+                Ain, Bin, esz = A32, B32, 4
+                code = sbg.R_32F
+                cmode = sbg.MODE_BF16X3 if mode == "bf16x3" else sbg.MODE_PLAIN
+            pA = torch.tensor(Ain.data_ptr() + offs["A"][0] * esz, device="cuda")
+            pB = torch.tensor(Bin.data_ptr() + offs["B"][0] * esz, device="cuda")
+
+            def call():
+                sbg.gemm_vbatched_ex("N", "N", dm, dn, dk, 16, 16, 16, 1.5, pA, dlda, sA, pB, dldb, sB, -0.5, pC,
+                                     dldc, N, code, cmode, ws)
+            C.copy_(C0)
+            gr = _graph(call, stream)
+            C.copy_(C0)
+            torch.cuda.synchronize()
+            gr.replay()                      # one clean replay for the deviation
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = C.clone()
+                dev_info = {"max_abs_dev_over_max_abs": 0.0}
+            else:
+                d = (C - ref).abs()
+                dev_info = {"max_abs_dev_over_max_abs": float(d.max() / ref.abs().max())}
+            med, mn = _time_replays(gr, 7, flush)
+            byts = float(np.sum((m64 * k64 + k64 * n64) * esz + 2 * m64 * n64 * 4)) + N * meta + \
+                (8 * N if mode == "e4m3" else 0)
+            results[mode] = {"us": round(med * 1e6, 1), "gflops": round(flops / med / 1e9, 1),
+                             "hbm_frac": round(byts / med / HBM_PEAK, 4), **dev_info}
+            if qtime is not None:
+                results[mode]["quantize_us"] = round(qtime * 1e6, 1)
+            del gr
+        res[dist] = results
+        del A32, B32, C0, C
+        torch.cuda.empty_cache()
+    return res
+
+
+def sec_fem_chain(stream):
+    """N = 1,000,000 FEM elements: K = B^T (D B) (two batched GEMMs) and its
+    backward from dK (four), each sequence captured as one HIP graph."""
+    import numpy as np
+    import torch
+
+    from paper_1304_7053_amd import inputs
+    from paper_1304_7053_amd.autograd import gemm_rm
+    N = 1_000_000
+    g = inputs.rng(5)
+    B, D, dK = (torch.from_numpy(x).cuda() for x in inputs.fem_element_batch(g, N))
+    T = torch.empty((N, 6, 12), device="cuda")
+    K = torch.empty((N, 12, 12), device="cuda")
+    dT = torch.empty_like(T)
+    dB = torch.empty_like(B)
+    dD = torch.empty_like(D)
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+
+    def fwd():
+        gemm_rm("N", "N", 1.0, D, B, 0.0, T)
+        gemm_rm("T", "N", 1.0, B, T, 0.0, K)
+
+    def bwd():
+        gemm_rm("N", "N", 1.0, B, dK, 0.0, dT)
+        gemm_rm("N", "T", 1.0, T, dK, 0.0, dB)
+        gemm_rm("T", "N", 1.0, D, dT, 1.0, dB)
+        gemm_rm("N", "T", 1.0, dT, B, 0.0, dD)
+    gf, gb = _graph(fwd, stream), _graph(bwd, stream)
+    tf, _ = _time_replays(gf, 7, flush)
+    tb, _ = _time_replays(gb, 7, flush)
+    ffl, bfl = 2592.0 * N, 5184.0 * N
+    fby, bby = 1872.0 * N, 4032.0 * N
+    del np
+    return {"workload": "N=1e6 elements, B 6x12, D 6x6, fp32",
+            "forward": {"us": round(tf * 1e6, 1), "gflops": round(ffl / tf / 1e9, 1),
+                        "hbm_frac": round(fby / tf / HBM_PEAK, 4)},
+            "backward": {"us": round(tb * 1e6, 1), "gflops": round(bfl / tb / 1e9, 1),
+                         "hbm_frac": round(bby / tb / HBM_PEAK, 4)}}
 
 
 def cpu_baseline(calls, sample):

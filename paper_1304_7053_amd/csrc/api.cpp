@@ -36,7 +36,7 @@ int device_cu_count()
 const Tuning& tuning()
 {
     static const Tuning t = [] {
-        Tuning v{8, 16, false};
+        Tuning v{8, 16, false, 8192};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;
@@ -46,6 +46,10 @@ const Tuning& tuning()
             if (x >= 1) v.xcd_chunk = x;
         }
         if (const char* e = std::getenv("SBG_STAGED")) v.staged = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SBG_TILE_BYTES")) {
+            int x = std::atoi(e);
+            if (x >= 256 && x <= (1 << 20)) v.tile_bytes = x;
+        }
         return v;
     }();
     return t;

@@ -31,7 +31,8 @@
 //  * Narrow inputs (bf16, fp16, fp8-e4m3 with per-matrix scales) are decoded
 //    exactly to binary32 as they are loaded; BF16x3 splits binary32 operands
 //    into bf16 hi + lo on the fly.  Accumulation is binary32.
-//  * Each wave keeps U tiles of loads in flight before it computes; the grid
+//  * Each wave keeps U tiles of loads in flight before it computes (U chosen
+//    per call from the actual sizes, about 8 KB per wave); the grid
 //    is persistent, and work-groups are renumbered so that each XCD (dispatch
 //    is round-robin over the 8 XCDs) takes runs of `xcd_chunk` consecutive
 //    tile groups, keeping cache lines shared by neighbouring matrices inside
@@ -140,10 +141,9 @@ inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
     return grid;
 }
 
-template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT, bool PTR>
-hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR>
+hipError_t launch_u(GemmArgs<T> a, hipStream_t stream)
 {
-    constexpr int U = Unroll<T, D>::value;
     constexpr int P = 16 / D;
     auto kern = gemm_mfma_kernel<T, TI, MODE, D, U, ACONT, BCONT, PTR>;
     const int64_t tiles = (a.batch + P - 1) / P;
@@ -151,6 +151,45 @@ hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
     const int64_t grid = persistent_grid(kern, groups, a);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
     return hipGetLastError();
+}
+
+// Largest tile unroll instantiated per element type and size class (bounded
+// by registers: the unrolled tiles' operands and accumulators stay resident).
+template <typename T, int D> struct UMax {
+    static constexpr int bytes = (int)sizeof(T);
+    static constexpr int value = bytes >= 16 ? (D == 16 ? 1 : (D == 8 ? 2 : 4))
+                               : bytes == 8 ? (D == 16 ? 2 : (D == 8 ? 4 : 8))
+                               : (D == 16 ? 4 : 8);
+};
+
+// Tiles per wave per step for the actual sizes: the largest power of two
+// (up to UMax) whose loads and stores stay within the per-wave byte target,
+// so partly filled tiles (e.g. n = 9 in the 16 class) keep as many bytes in
+// flight as full ones.
+template <typename T, typename TI, int D>
+inline int choose_unroll(const GemmArgs<T>& a)
+{
+    const int64_t P = 16 / D;
+    const int64_t tile = P * ((int64_t)(a.m * a.k + a.k * a.n) * (int64_t)sizeof(TI) +
+                              2 * (int64_t)a.m * a.n * (int64_t)sizeof(T));
+    const int64_t target = tuning().tile_bytes;
+    int U = 1;
+    while (U * 2 <= UMax<T, D>::value && (U * 2) * tile <= target) U *= 2;
+    return U;
+}
+
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT, bool PTR>
+hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
+{
+    constexpr int UM = UMax<T, D>::value;
+    const int U = choose_unroll<T, TI, D>(a);
+    if constexpr (UM >= 8)
+        if (U == 8) return launch_u<T, TI, MODE, D, 8, ACONT, BCONT, PTR>(a, stream);
+    if constexpr (UM >= 4)
+        if (U == 4) return launch_u<T, TI, MODE, D, 4, ACONT, BCONT, PTR>(a, stream);
+    if constexpr (UM >= 2)
+        if (U == 2) return launch_u<T, TI, MODE, D, 2, ACONT, BCONT, PTR>(a, stream);
+    return launch_u<T, TI, MODE, D, 1, ACONT, BCONT, PTR>(a, stream);
 }
 
 template <typename T, int D, bool ACONT, bool BCONT>
@@ -244,7 +283,7 @@ int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
     if (!pointer_form && tuning().staged && is_packed(a))
         return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %d, %s, %s>(sbg::GemmArgs<%s>)",
                         TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
-    const int U = D == 4 ? Unroll<T, 4>::value : (D == 8 ? Unroll<T, 8>::value : Unroll<T, 16>::value);
+    const int U = D == 4 ? choose_unroll<T, T, 4>(a) : (D == 8 ? choose_unroll<T, T, 8>(a) : choose_unroll<T, T, 16>(a));
     return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
                     TypeName<T>::s, TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form),
                     TypeName<T>::s);

@@ -1,0 +1,12 @@
+// Mixed-precision kernel instances: A and B stored as bf16_t, mode 0 (see gemm_ex.hip).
+#include "gemm_vbatched.h"
+
+namespace sbg {
+
+hipError_t launch_ex_bf16(const GemmArgs<float>& a, int form, hipStream_t s)
+{
+    if (form == 2) return launch_vbatched_t<float, bf16_t, 0>(a, s);
+    return launch_direct<float, bf16_t, 0>(a, form == 1, s);
+}
+
+}  // namespace sbg

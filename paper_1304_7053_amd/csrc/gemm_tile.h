@@ -31,6 +31,7 @@ template <typename R> struct Mfma;
 template <> struct Mfma<float> {
     using acc_t = f32x4;
     static constexpr bool rows_contig = true;
+    static constexpr bool swap = false;
     static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
     static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -39,6 +40,11 @@ template <> struct Mfma<float> {
 template <> struct Mfma<double> {
     using acc_t = f64x4;
     static constexpr bool rows_contig = false;
+    // The f64 result rows of a lane are 4 apart; feeding op(B) as the MFMA's
+    // first operand and op(A) as its second makes the accumulator hold C^T,
+    // so the 16 lanes of a group hold 16 consecutive rows of one C column
+    // (128 contiguous bytes per store instruction and group).
+    static constexpr bool swap = true;
     static __device__ __forceinline__ int row(int g, int r) { return 4 * r + g; }
     static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -146,7 +152,9 @@ __device__ __forceinline__ T axpby(typename Tr<T>::R ar, typename Tr<T>::R ai, t
     return make_val<T>(tr, ti);
 }
 
-// One lane's view of the matrix it serves in a tile.
+// One lane's view of the matrix it serves in a tile.  Output register r of
+// the lane holds C(i, j) with (i, j) = (orow[r], ij), or (ij, orow[r]) when
+// the MFMA operands are swapped.
 template <typename T, typename TI>
 struct LaneMat {
     const TI* A;
@@ -268,14 +276,22 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
 #pragma unroll
         for (int r = 0; r < 4; ++r) cin[u][r] = make_val<T>(R(0), R(0));
         crun[u] = M::rows_contig && L.keep[0] && col_ok && (L.orow[0] + 3) < mt.m;
-        if (!b0 && mt.valid && col_ok) {
-            const T* cb = mt.C + L.ij * mt.ldc;
-            if (crun[u]) {
-                vload<T, 4>(cin[u], cb + L.orow[0]);
-            } else {
+        if (!b0 && mt.valid) {
+            if (M::swap) {
+                if (row_ok) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (L.keep[r] && L.orow[r] < mt.m) cin[u][r] = cb[L.orow[r]];
+                    for (int r = 0; r < 4; ++r)
+                        if (L.keep[r] && L.orow[r] < mt.n) cin[u][r] = mt.C[L.ij + L.orow[r] * mt.ldc];
+                }
+            } else if (col_ok) {
+                const T* cb = mt.C + L.ij * mt.ldc;
+                if (crun[u]) {
+                    vload<T, 4>(cin[u], cb + L.orow[0]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (L.keep[r] && L.orow[r] < mt.m) cin[u][r] = cb[L.orow[r]];
+                }
             }
         }
     }
@@ -296,6 +312,13 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
                     acc_r = M::run(ah, bh, acc_r);
                     acc_r = M::run(ah, bl, acc_r);
                     acc_r = M::run(al, bh, acc_r);
+                } else if (M::swap) {
+                    acc_r = M::run(xb_r[u][kb], xa_r[u][kb], acc_r);
+                    if (CPLX) {
+                        acc_r = M::run(xb_i[u][kb], -xa_i[u][kb], acc_r);
+                        acc_i = M::run(xb_i[u][kb], xa_r[u][kb], acc_i);
+                        acc_i = M::run(xb_r[u][kb], xa_i[u][kb], acc_i);
+                    }
                 } else {
                     acc_r = M::run(xa_r[u][kb], xb_r[u][kb], acc_r);
                     if (CPLX) {
@@ -306,8 +329,8 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
                 }
             }
         }
-        const bool col_ok = L.ij < mt.n;
-        if (!(mt.valid && col_ok)) continue;
+        const bool lane_ok = M::swap ? (L.ij < mt.m) : (L.ij < mt.n);
+        if (!(mt.valid && lane_ok)) continue;
         // scaled narrow inputs: alpha * sA * sB applied as (alpha sA sB) * acc
         R ar = ar_, ai = ai_;
         if (!CPLX && mt.scale != 1.0f) ar = ar_ * (R)mt.scale;
@@ -315,13 +338,19 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
 #pragma unroll
         for (int r = 0; r < 4; ++r)
             out[r] = axpby<T>(ar, ai, br_, bi_, a0, b0, acc_r[r], acc_i[r], cin[u][r]);
-        T* cb = mt.C + L.ij * mt.ldc;
-        if (crun[u]) {
-            vstore<T, 4>(cb + L.orow[0], out);
-        } else {
+        if (M::swap) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (L.keep[r] && L.orow[r] < mt.m) cb[L.orow[r]] = out[r];
+                if (L.keep[r] && L.orow[r] < mt.n) mt.C[L.ij + L.orow[r] * mt.ldc] = out[r];
+        } else {
+            T* cb = mt.C + L.ij * mt.ldc;
+            if (crun[u]) {
+                vstore<T, 4>(cb + L.orow[0], out);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (L.keep[r] && L.orow[r] < mt.m) cb[L.orow[r]] = out[r];
+            }
         }
     }
 }
