@@ -228,6 +228,21 @@ int sbg_last_invalid_arg(void);
 const char* sbg_status_string(sbg_status_t status);
 int sbg_version(void);
 
+/* ---- launch tuning ----------------------------------------------------------
+ * Process-wide knobs of the kernel selection and launch shape, for tuning
+ * sweeps and A/B comparisons (not thread-safe against concurrent calls; set
+ * them before launching).  Keys: "wg_per_cu" (persistent work-groups per CU,
+ * 1..32), "xcd_chunk" (consecutive work units per XCD run, >= 1), "staged"
+ * (0/1: packed strided batches through the LDS-staged kernel), "tile_bytes"
+ * (per-wave bytes in flight that choose the tile unroll, 256..2^20),
+ * "pipeline" (0/1: prefetch the next tile group in the direct kernel).
+ * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
+ * SBG_TILE_BYTES, SBG_PIPELINE set the initial values.
+ * sbg_set_tuning returns the previous value, or -1 for an unknown key or an
+ * out-of-range value (nothing changed); sbg_get_tuning returns the value or -1. */
+int sbg_set_tuning(const char* key, int value);
+int sbg_get_tuning(const char* key);
+
 /* ---- diagnostics --------------------------------------------------------
  * sbg_describe_strided: validates the arguments of a strided call (prefix
  *   's', 'd', 'c' or 'z' selects the entry point; alpha = 1, beta = 0.5 are

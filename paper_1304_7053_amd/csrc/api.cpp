@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "sbg.h"
@@ -33,10 +34,10 @@ int device_cu_count()
     return cache[dev];
 }
 
-const Tuning& tuning()
+Tuning& tuning_mut()
 {
-    static const Tuning t = [] {
-        Tuning v{8, 16, false, 8192};
+    static Tuning t = [] {
+        Tuning v{8, 16, false, 8192, false};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;
@@ -46,6 +47,7 @@ const Tuning& tuning()
             if (x >= 1) v.xcd_chunk = x;
         }
         if (const char* e = std::getenv("SBG_STAGED")) v.staged = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SBG_PIPELINE")) v.pipeline = std::atoi(e) != 0;
         if (const char* e = std::getenv("SBG_TILE_BYTES")) {
             int x = std::atoi(e);
             if (x >= 256 && x <= (1 << 20)) v.tile_bytes = x;
@@ -54,6 +56,8 @@ const Tuning& tuning()
     }();
     return t;
 }
+
+const Tuning& tuning() { return tuning_mut(); }
 
 namespace {
 
@@ -577,6 +581,49 @@ int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, in
     sbg::tl_describe_buf = nullptr;
     sbg::tl_describe_len = 0;
     return st == SBG_OK && buf[0] ? 0 : -1;
+}
+
+int sbg_set_tuning(const char* key, int value)
+{
+    if (!key) return -1;
+    sbg::Tuning& t = sbg::tuning_mut();
+    const std::string k(key);
+    int old;
+    if (k == "wg_per_cu") {
+        if (value < 1 || value > 32) return -1;
+        old = t.wg_per_cu;
+        t.wg_per_cu = value;
+    } else if (k == "xcd_chunk") {
+        if (value < 1) return -1;
+        old = t.xcd_chunk;
+        t.xcd_chunk = value;
+    } else if (k == "staged") {
+        old = t.staged ? 1 : 0;
+        t.staged = value != 0;
+    } else if (k == "tile_bytes") {
+        if (value < 256 || value > (1 << 20)) return -1;
+        old = t.tile_bytes;
+        t.tile_bytes = value;
+    } else if (k == "pipeline") {
+        old = t.pipeline ? 1 : 0;
+        t.pipeline = value != 0;
+    } else {
+        return -1;
+    }
+    return old;
+}
+
+int sbg_get_tuning(const char* key)
+{
+    if (!key) return -1;
+    const sbg::Tuning& t = sbg::tuning();
+    const std::string k(key);
+    if (k == "wg_per_cu") return t.wg_per_cu;
+    if (k == "xcd_chunk") return t.xcd_chunk;
+    if (k == "staged") return t.staged ? 1 : 0;
+    if (k == "tile_bytes") return t.tile_bytes;
+    if (k == "pipeline") return t.pipeline ? 1 : 0;
+    return -1;
 }
 
 void sbg_set_scalar_mode(sbg_scalar_mode_t mode)

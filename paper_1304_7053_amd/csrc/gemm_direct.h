@@ -53,8 +53,9 @@ template <typename T> __device__ __forceinline__ void load_scalars(const GemmArg
     beta = a.beta_dev ? *a.beta_dev : a.beta;
 }
 
-// TI: stored type of A and B; MODE: 0 plain, 1 BF16x3; PTR: pointer-array form.
-template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR>
+// TI: stored type of A and B; MODE: 0 plain, 1 BF16x3; PTR: pointer-array
+// form; PIPE: issue the next group's loads before computing the current one.
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR, bool PIPE>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
 {
     using R = typename Tr<T>::R;
@@ -69,8 +70,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
     const int64_t ntiles = (a.batch + P - 1) / P;
     const int64_t ngroups = (ntiles + U - 1) / U;
 
-    for (int64_t grp = q; grp < ngroups; grp += W) {
-        LaneMat<T, TI> mats[U];
+    // the matrices this lane serves in the U tiles of group grp
+    auto setup = [&](int64_t grp, LaneMat<T, TI> (&mats)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t p = ((grp * U + u) * P) + L.sel;
@@ -101,7 +102,35 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
                 if (a.scaleA) mt.scale = a.scaleA[p] * a.scaleB[p];
             }
         }
-        tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
+    };
+
+    if (!PIPE) {
+        for (int64_t grp = q; grp < ngroups; grp += W) {
+            LaneMat<T, TI> mats[U];
+            setup(grp, mats);
+            tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
+        }
+        return;
+    }
+    // software pipeline across groups: loads of group grp + W are in flight
+    // while group grp is multiplied and stored
+    if (q >= ngroups) return;
+    LaneMat<T, TI> cur[U], nxt[U];
+    TileRegs<T, TI, D, U> rc, rn;
+    setup(q, cur);
+    tile_load<T, TI, D, U, ACONT, BCONT>(cur, L, a0, b0, rc);
+    for (int64_t grp = q; grp < ngroups; grp += W) {
+        const bool more = grp + W < ngroups;
+        if (more) {
+            setup(grp + W, nxt);
+            tile_load<T, TI, D, U, ACONT, BCONT>(nxt, L, a0, b0, rn);
+        }
+        tile_finish<T, TI, MODE, D, U>(cur, L, alpha, beta, a0, b0, a.a_conj, a.b_conj, rc);
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+            rc = rn;
+        }
     }
 }
 
@@ -141,16 +170,23 @@ inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
     return grid;
 }
 
-template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR>
-hipError_t launch_u(GemmArgs<T> a, hipStream_t stream)
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR, bool PIPE>
+hipError_t launch_up(GemmArgs<T> a, hipStream_t stream)
 {
     constexpr int P = 16 / D;
-    auto kern = gemm_mfma_kernel<T, TI, MODE, D, U, ACONT, BCONT, PTR>;
+    auto kern = gemm_mfma_kernel<T, TI, MODE, D, U, ACONT, BCONT, PTR, PIPE>;
     const int64_t tiles = (a.batch + P - 1) / P;
     const int64_t groups = (tiles + U - 1) / U;
     const int64_t grid = persistent_grid(kern, groups, a);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
     return hipGetLastError();
+}
+
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, bool PTR>
+hipError_t launch_u(GemmArgs<T> a, hipStream_t stream)
+{
+    if (tuning().pipeline) return launch_up<T, TI, MODE, D, U, ACONT, BCONT, PTR, true>(a, stream);
+    return launch_up<T, TI, MODE, D, U, ACONT, BCONT, PTR, false>(a, stream);
 }
 
 // Largest tile unroll instantiated per element type and size class (bounded
@@ -192,9 +228,9 @@ hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
     return launch_u<T, TI, MODE, D, 1, ACONT, BCONT, PTR>(a, stream);
 }
 
-template <typename T, int D, bool ACONT, bool BCONT>
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream);
-template <typename T>
+template <typename T, typename TI>
 int staged_run_length(int m, int n, int k, int64_t batch, int min_waves);
 
 template <typename T, typename TI, int MODE, int D, bool PTR>
@@ -227,10 +263,36 @@ inline bool is_packed(const GemmArgs<T>& a)
            a.strideB == rb * cb && a.strideC == (int64_t)a.m * a.n;
 }
 
+template <typename T, typename TI, int MODE, int D>
+hipError_t launch_staged_ops(const GemmArgs<T>& a, hipStream_t stream)
+{
+    const bool at = a.a_trans, bn = !a.b_trans;
+    if (at) return bn ? launch_staged<T, TI, MODE, D, true, true>(a, stream)
+                      : launch_staged<T, TI, MODE, D, true, false>(a, stream);
+    return bn ? launch_staged<T, TI, MODE, D, false, true>(a, stream)
+              : launch_staged<T, TI, MODE, D, false, false>(a, stream);
+}
+
+// Matrices per staged run for this call, or 0 to use the direct kernel.
+template <typename T, typename TI>
+inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
+{
+    if (pointer_form || !tuning().staged || !is_packed(a) || a.scaleA) return 0;
+    return staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
+}
+
+// Strided / pointer-array dispatch: packed strided batches go through the
+// LDS-staged kernel (when enabled), everything else through the direct one.
 template <typename T, typename TI, int MODE>
 hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
     const int D = size_class(a.m, a.n, a.k);
+    a.G = staged_choice<T, TI>(a, pointer_form);
+    if (a.G > 0) {
+        if (D == 4) return launch_staged_ops<T, TI, MODE, 4>(a, stream);
+        if (D == 8) return launch_staged_ops<T, TI, MODE, 8>(a, stream);
+        return launch_staged_ops<T, TI, MODE, 16>(a, stream);
+    }
     if (pointer_form) {
         if (D == 4) return launch_ops<T, TI, MODE, 4, true>(a, stream);
         if (D == 8) return launch_ops<T, TI, MODE, 8, true>(a, stream);
@@ -241,29 +303,10 @@ hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
     return launch_ops<T, TI, MODE, 16, false>(a, stream);
 }
 
-// Plain S/D/C/Z: the LDS-staged kernel for packed batches when enabled,
-// otherwise the direct kernel.
+// Plain S/D/C/Z.
 template <typename T>
 hipError_t launch_gemm_impl(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
-    a.G = 0;
-    if (!pointer_form && tuning().staged && is_packed(a))
-        a.G = staged_run_length<T>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
-    if (a.G > 0) {
-        const int D = size_class(a.m, a.n, a.k);
-        const bool at = a.a_trans, bn = !a.b_trans;
-#define SBG_STAGED_OPS(DD)                                                                   \
-    if (D == DD) {                                                                           \
-        if (at) return bn ? launch_staged<T, DD, true, true>(a, stream)                      \
-                          : launch_staged<T, DD, true, false>(a, stream);                    \
-        return bn ? launch_staged<T, DD, false, true>(a, stream)                             \
-                  : launch_staged<T, DD, false, false>(a, stream);                           \
-    }
-        SBG_STAGED_OPS(4)
-        SBG_STAGED_OPS(8)
-        SBG_STAGED_OPS(16)
-#undef SBG_STAGED_OPS
-    }
     return launch_direct<T, T, 0>(a, pointer_form, stream);
 }
 
@@ -280,13 +323,13 @@ int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
 {
     const auto tf = [](bool b) { return b ? "true" : "false"; };
     const int D = size_class(a.m, a.n, a.k);
-    if (!pointer_form && tuning().staged && is_packed(a))
-        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %d, %s, %s>(sbg::GemmArgs<%s>)",
-                        TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
+    if (staged_choice<T, T>(a, pointer_form) > 0)
+        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %s, 0, %d, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
     const int U = D == 4 ? choose_unroll<T, T, 4>(a) : (D == 8 ? choose_unroll<T, T, 8>(a) : choose_unroll<T, T, 16>(a));
-    return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
+    return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s, %s>(sbg::GemmArgs<%s>)",
                     TypeName<T>::s, TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form),
-                    TypeName<T>::s);
+                    tf(tuning().pipeline), TypeName<T>::s);
 }
 
 }  // namespace sbg

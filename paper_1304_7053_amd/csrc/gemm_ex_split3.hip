@@ -1,5 +1,6 @@
 // Mixed-precision kernel instances: A and B stored as float, mode 1 (see gemm_ex.hip).
 #include "gemm_vbatched.h"
+#include "gemm_staged.h"
 
 namespace sbg {
 

@@ -1,23 +1,23 @@
-// Batched small-matrix GEMM for PACKED strided batches (lda = rows of A,
-// strideA = rows * cols, likewise for B and C -- the minimal leading
-// dimensions of the paper's experiments, Sec. 8), staged through LDS.
+// Batched small-matrix GEMM for PACKED strided batches (lda = stored rows of
+// A, strideA = rows * cols, likewise for B and C: the minimal leading
+// dimensions of the paper's experiments, Sec. 8), streamed through LDS.
 //
-// In a packed batch any run of consecutive matrices is one contiguous span of
-// each operand.  A wave therefore moves G matrices per step as three flat
-// streams:
-//   1. HBM -> registers -> LDS: every lane copies 16-byte chunks of the A, B
-//      (and, when beta != 0, C) spans; consecutive lanes take consecutive
-//      chunks, so each load instruction reads 1 KB of contiguous memory
-//      whatever m, n, k are (no per-size coalescing problem, no masks but
-//      the span ends);
-//   2. LDS -> MFMA operand registers: the same block-diagonal packing as the
-//      direct kernel (16/D matrices of size class D per 16x16x16 product),
-//      gathered from LDS with the op folded into the addressing;
-//   3. results are written back into the C span in LDS and leave as one
-//      contiguous, fully written span of 16-byte stores.
-// G is chosen on the host so that the three spans fill the wave's LDS slice;
-// small matrices thus move as many bytes per step as large ones.  Each wave
-// owns its LDS slice: no work-group barriers, only wave-level ordering.
+// In a packed batch a run of G consecutive matrices is one contiguous span of
+// each operand.  Each wavefront owns an LDS slice and processes runs:
+//   1. spans -> registers: lane i loads 16-byte chunks i, i+64, ... of the
+//      A, B (and, when beta != 0, C) spans as one flat chunk list.  Every load
+//      is unconditional: a chunk index past the end is clamped to the last
+//      chunk, and the last chunk of a span starts 16 bytes before the span's
+//      end (overlapping its neighbour), so no access leaves the span and no
+//      load sits behind a lane mask;
+//   2. registers -> LDS; the next run's chunk loads are issued right away
+//      and stay in flight while this run computes;
+//   3. LDS -> MFMA operands (the block-diagonal packing of the direct kernel:
+//      16/D matrices of size class D per 16x16x16 product), results written
+//      back into the C span in LDS;
+//   4. C span LDS -> HBM with the same clamped 16-byte chunks.
+// Whatever m, n, k are, every global access of a wave is a 1 KB contiguous
+// stream; small matrices move as many bytes per wave step as large ones.
 #pragma once
 
 #include "gemm_direct.h"
@@ -26,7 +26,7 @@ namespace sbg {
 
 template <typename T> struct StagedCfg {
     static constexpr int LDSW = sizeof(T) >= 16 ? 16384 : 8192;  // LDS bytes per wave
-    static constexpr int MAXCH = LDSW / 1024;                     // 16-B chunks per lane
+    static constexpr int MAXCH = LDSW / 1024;                     // 16-B chunks per lane (bound)
 };
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -36,287 +36,214 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int align16(int x) { return (x + 15) & ~15; }
+__host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 
-template <typename T, int D, bool ACONT, bool BCONT>
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
 {
     using R = typename Tr<T>::R;
-    using M = Mfma<R>;
-    using acc_t = typename M::acc_t;
     using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
-    constexpr bool CPLX = Tr<T>::cplx;
+    // 16-byte vector at 4-byte alignment (chunk boundaries follow the spans)
+    typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
     constexpr int P = 16 / D;
-    constexpr int KB = D / 4;
     constexpr int LDSW = StagedCfg<T>::LDSW;
     constexpr int MAXCH = StagedCfg<T>::MAXCH;
-    constexpr int ESZ = (int)sizeof(T);
+    constexpr int EI = (int)sizeof(TI);
+    constexpr int EC = (int)sizeof(T);
 
     __shared__ __attribute__((aligned(16))) unsigned char lds_all[4 * LDSW];
     unsigned char* lds = lds_all + (threadIdx.x >> 6) * LDSW;
-
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4;
-    const int c = lane & 15;
-    const int sel = c / D;
-    const int ij = c % D;
-    const int kk0 = KB * g;
+    const LaneGeom<D, R> L;
 
-    const T alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
-    const T beta = a.beta_dev ? *a.beta_dev : a.beta;
-    const bool a0 = is_zero(alpha);
-    const bool b0 = is_zero(beta);
-    const R ar_ = re_of<T>(alpha), ai_ = im_of<T>(alpha);
-    const R br_ = re_of<T>(beta), bi_ = im_of<T>(beta);
+    T alpha, beta;
+    load_scalars(a, alpha, beta);
+    const bool a0 = is_zero(alpha), b0 = is_zero(beta);
 
     const int m = a.m, n = a.n, k = a.k;
     const int eA = m * k, eB = k * n, eC = m * n;   // elements per matrix
     const int G = a.G;
-    const int offB = align16(G * eA * ESZ);
-    const int offC = offB + align16(G * eB * ESZ);
-    const bool row_ok = ij < m;
-    const bool col_ok = ij < n;
-
-    bool keep[4];
-    int orow[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int Rr = M::row(g, r);
-        keep[r] = (Rr / D) == sel && (Rr % D) < m && col_ok;
-        orow[r] = Rr % D;
-    }
+    const int offB = align16i(G * eA * EI);
+    const int offC = offB + align16i(G * eB * EI);
 
     const int64_t W = (int64_t)gridDim.x * 4;
-    const int64_t q0 = xcd_wave_index(a.xcd_chunk);
-    const int64_t nsteps = (a.batch + G - 1) / G;
+    const int64_t nruns = (a.batch + G - 1) / G;
+    const unsigned char* gA0 = static_cast<const unsigned char*>(a.A);
+    const unsigned char* gB0 = static_cast<const unsigned char*>(a.B);
+    unsigned char* gC0 = reinterpret_cast<unsigned char*>(a.C);
 
-    // One run = G consecutive matrices; its spans and their chunk counts.
-    struct Run {
-        int cnt, bytesA, bytesB, bytesC, bytesCin, FA, FB, FC;
-        const unsigned char* gA;
-        const unsigned char* gB;
-        unsigned char* gC;
-    };
-    auto make_run = [&](int64_t step) {
-        Run r;
-        const int64_t p0 = step * G;
-        r.cnt = (int)((a.batch - p0) < G ? (a.batch - p0) : G);
-        if (r.cnt < 0) r.cnt = 0;
-        r.gA = reinterpret_cast<const unsigned char*>(static_cast<const T*>(a.A) + p0 * eA);
-        r.gB = reinterpret_cast<const unsigned char*>(static_cast<const T*>(a.B) + p0 * eB);
-        r.gC = reinterpret_cast<unsigned char*>(a.C + p0 * eC);
-        r.bytesA = a0 ? 0 : r.cnt * eA * ESZ;
-        r.bytesB = a0 ? 0 : r.cnt * eB * ESZ;
-        r.bytesC = r.cnt * eC * ESZ;
-        r.bytesCin = b0 ? 0 : r.bytesC;
-        r.FA = r.bytesA >> 4;
-        r.FB = r.bytesB >> 4;
-        r.FC = r.bytesCin >> 4;
-        return r;
-    };
+    // Spans of run r (the last run may be shorter; every span is >= 16 bytes
+    // of whole words, which the host guarantees): byte sizes SA, SB, SCin
+    // (loaded) and SC (stored), chunk counts FX = ceil(SX / 16).
+    // the run index is wave-uniform: keep it (and all span arithmetic) scalar
+    const int64_t r0 = xcd_wave_index(a.xcd_chunk);
+    int64_t r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0 >> 32)) << 32) |
+                (uint32_t)__builtin_amdgcn_readfirstlane((int)(r0 & 0xFFFFFFFF));
+    if (r >= nruns) return;
 
     u32x4 buf[MAXCH];
-    unsigned int tail = 0;
-    int tail_off = -1;
+    int cnt = 0, SA = 0, SB = 0, SC = 0, SCin = 0, FA = 0, FB = 0, FT = 0;
+    const unsigned char* gA = nullptr;
+    const unsigned char* gB = nullptr;
+    unsigned char* gC = nullptr;
 
-    // HBM -> registers: 16-byte chunks of the A, B, C spans (lane-consecutive),
-    // then the < 16-byte span tails (lanes 0-3 A, 4-7 B, 8-11 C).
-    auto issue_loads = [&](const Run& r) {
+#define SBG_RUN_SPANS(RR)                                                           \
+    {                                                                               \
+        const int64_t p0 = (RR) * G;                                                \
+        cnt = (int)((a.batch - p0) < G ? (a.batch - p0) : G);                       \
+        gA = gA0 + p0 * eA * EI;                                                    \
+        gB = gB0 + p0 * eB * EI;                                                    \
+        gC = gC0 + p0 * eC * EC;                                                    \
+        SA = a0 ? 0 : cnt * eA * EI;                                                \
+        SB = a0 ? 0 : cnt * eB * EI;                                                \
+        SC = cnt * eC * EC;                                                         \
+        SCin = b0 ? 0 : SC;                                                         \
+        FA = (SA + 15) >> 4;                                                        \
+        FB = (SB + 15) >> 4;                                                        \
+        FT = FA + FB + ((SCin + 15) >> 4);                                          \
+    }
+    // chunk q (clamped to the list) of A | B | C: byte offset inside its span
+    // (the last chunk of a span ends at the span's end), source and LDS address
+#define SBG_CHUNK(Q, SRC, DST)                                                      \
+    {                                                                               \
+        const int q_ = (Q) < FT ? (Q) : FT - 1;                                     \
+        const bool inA = q_ < FA;                                                   \
+        const bool inB = !inA && q_ < FA + FB;                                      \
+        const int loc = inA ? q_ : (inB ? q_ - FA : q_ - FA - FB);                  \
+        const int S_ = inA ? SA : (inB ? SB : SCin);                                \
+        const int off = (16 * loc + 16 <= S_) ? 16 * loc : S_ - 16;                 \
+        SRC = (inA ? gA : (inB ? gB : (const unsigned char*)gC)) + off;             \
+        DST = (inA ? 0 : (inB ? offB : offC)) + off;                                \
+    }
+
+    // The chunk loops below run MAXCH times unconditionally: indices past
+    // the list re-read (and re-write to LDS) the clamped last chunk, so the
+    // loads carry no branches and the compiler counts them exactly.
+    // With alpha == 0 and beta == 0 nothing is loaded (FT == 0): the chunk
+    // loops are skipped, since a clamped index would otherwise be -1.
+    SBG_RUN_SPANS(r)
+    if (FT > 0) {
 #pragma unroll
         for (int t = 0; t < MAXCH; ++t) {
-            const int qq = lane + 64 * t;
             const unsigned char* src;
-            if (qq < r.FA) src = r.gA + 16 * qq;
-            else if (qq < r.FA + r.FB) src = r.gB + 16 * (qq - r.FA);
-            else src = r.gC + 16 * (qq - r.FA - r.FB);
-            if (qq < r.FA + r.FB + r.FC)
-                __builtin_memcpy(&buf[t], reinterpret_cast<const unsigned int*>(src), 16);
-        }
-        tail_off = -1;
-        const int which = lane >> 2, w = lane & 3;
-        if (which < 3) {
-            const int bytes = which == 0 ? r.bytesA : (which == 1 ? r.bytesB : r.bytesCin);
-            const int F = bytes >> 4;
-            const int tw = (bytes & 15) >> 2;
-            if (w < tw) {
-                const unsigned char* base = which == 0 ? r.gA : (which == 1 ? r.gB : r.gC);
-                tail = reinterpret_cast<const unsigned int*>(base + 16 * F)[w];
-                tail_off = (which == 0 ? 0 : (which == 1 ? offB : offC)) + 16 * F + 4 * w;
-            }
-        }
-    };
-    // registers -> this wave's LDS slice
-    auto commit = [&](const Run& r) {
-#pragma unroll
-        for (int t = 0; t < MAXCH; ++t) {
-            const int qq = lane + 64 * t;
             int dst;
-            if (qq < r.FA) dst = 16 * qq;
-            else if (qq < r.FA + r.FB) dst = offB + 16 * (qq - r.FA);
-            else dst = offC + 16 * (qq - r.FA - r.FB);
-            if (qq < r.FA + r.FB + r.FC) *reinterpret_cast<u32x4*>(lds + dst) = buf[t];
+            SBG_CHUNK(lane + 64 * t, src, dst)
+            (void)dst;
+            buf[t] = *reinterpret_cast<const u32x4a4*>(src);
         }
-        if (tail_off >= 0) *reinterpret_cast<unsigned int*>(lds + tail_off) = tail;
-    };
+    }
 
-    const T* lA = reinterpret_cast<const T*>(lds);
-    const T* lB = reinterpret_cast<const T*>(lds + offB);
+    const TI* lA = reinterpret_cast<const TI*>(lds);
+    const TI* lB = reinterpret_cast<const TI*>(lds + offB);
     T* lC = reinterpret_cast<T*>(lds + offC);
 
-    // One tile (P matrices of the run starting at index mi0): operands from
-    // LDS into MFMA registers.
-    struct Ops { R ar[KB], ai[KB], br[KB], bi[KB]; };
-    auto gather = [&](int mi, int cnt, Ops& o) {
-        const bool mv = mi < cnt;
+    for (; r < nruns; r += W) {
+        // registers -> LDS for this run
+        if (FT > 0) {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            const int kk = kk0 + kb;
-            T va = make_val<T>(R(0), R(0)), vb = make_val<T>(R(0), R(0));
-            if (mv && kk < k) {
-                if (row_ok) va = lA[mi * eA + (ACONT ? kk + ij * k : ij + kk * m)];
-                if (col_ok) vb = lB[mi * eB + (BCONT ? kk + ij * k : ij + kk * n)];
-            }
-            o.ar[kb] = re_of<T>(va);
-            o.br[kb] = re_of<T>(vb);
-            if (CPLX) {
-                o.ai[kb] = im_of<T>(va) * (R)a.a_conj;
-                o.bi[kb] = im_of<T>(vb) * (R)a.b_conj;
-            } else {
-                o.ai[kb] = 0;
-                o.bi[kb] = 0;
+            for (int t = 0; t < MAXCH; ++t) {
+                const unsigned char* src;
+                int dst;
+                SBG_CHUNK(lane + 64 * t, src, dst)
+                (void)src;
+                *reinterpret_cast<u32x4a4*>(lds + dst) = buf[t];
             }
         }
-    };
-    auto product = [&](const Ops& o, acc_t& acc_r, acc_t& acc_i) {
+        wave_lds_sync();
+        const int ccnt = cnt, cSC = SC;
+        unsigned char* cgC = gC;
+        // next run's chunks: in flight while this run computes
+        if (r + W < nruns) {
+            SBG_RUN_SPANS(r + W)
+            if (FT > 0) {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            acc_r = M::run(o.ar[kb], o.br[kb], acc_r);
-            if (CPLX) {
-                acc_r = M::run(-o.ai[kb], o.bi[kb], acc_r);
-                acc_i = M::run(o.ar[kb], o.bi[kb], acc_i);
-                acc_i = M::run(o.ai[kb], o.br[kb], acc_i);
-            }
-        }
-    };
-    // epilogue of one tile: C_in from LDS (if beta != 0), result back to LDS
-    auto finish = [&](int mi, int cnt, const acc_t& acc_r, const acc_t& acc_i) {
-        if (mi >= cnt) return;
-        T* cm = lC + mi * eC + ij * m;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (!keep[r]) continue;
-            R cr = 0, ci = 0;
-            if (!b0) {
-                const T cv = cm[orow[r]];
-                cr = re_of<T>(cv);
-                ci = im_of<T>(cv);
-            }
-            R outr, outi = 0;
-            if (!CPLX) {
-                if (a0)
-                    outr = b0 ? R(0) : br_ * cr;
-                else if (b0)
-                    outr = ar_ * acc_r[r];
-                else
-                    outr = __builtin_fma(ar_, acc_r[r], br_ * cr);
-            } else {
-                R tr = 0, ti = 0;
-                if (!b0) {
-                    tr = __builtin_fma(br_, cr, -(bi_ * ci));
-                    ti = __builtin_fma(br_, ci, bi_ * cr);
+                for (int t = 0; t < MAXCH; ++t) {
+                    const unsigned char* src;
+                    int dst;
+                    SBG_CHUNK(lane + 64 * t, src, dst)
+                    (void)dst;
+                    buf[t] = *reinterpret_cast<const u32x4a4*>(src);
                 }
-                if (!a0) {
-                    tr = __builtin_fma(ar_, acc_r[r], __builtin_fma(-ai_, acc_i[r], tr));
-                    ti = __builtin_fma(ar_, acc_i[r], __builtin_fma(ai_, acc_r[r], ti));
-                }
-                outr = tr;
-                outi = ti;
             }
-            cm[orow[r]] = make_val<T>(outr, outi);
         }
-    };
-
-    Run cur = make_run(q0);
-    if (q0 < nsteps) issue_loads(cur);
-    for (int64_t step = q0; step < nsteps; step += W) {
-        commit(cur);
-        wave_lds_sync();
-        // prefetch the next run into registers while this one is processed
-        const Run nxt = make_run(step + W);
-        if (step + W < nsteps) issue_loads(nxt);
-
-        // tiles of the run, two at a time so their LDS reads overlap
-        const int ntiles = (cur.cnt + P - 1) / P;
-        int tile = 0;
-        for (; tile + 1 < ntiles; tile += 2) {
-            Ops o0, o1;
-            acc_t r0 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
-            if (!a0) {
-                gather(tile * P + sel, cur.cnt, o0);
-                gather((tile + 1) * P + sel, cur.cnt, o1);
-                product(o0, r0, i0);
-                product(o1, r1, i1);
-            }
-            finish(tile * P + sel, cur.cnt, r0, i0);
-            finish((tile + 1) * P + sel, cur.cnt, r1, i1);
-        }
-        if (tile < ntiles) {
-            Ops o0;
-            acc_t r0 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0};
-            if (!a0) {
-                gather(tile * P + sel, cur.cnt, o0);
-                product(o0, r0, i0);
-            }
-            finish(tile * P + sel, cur.cnt, r0, i0);
+        // tiles of the run from LDS: each lane's matrix mi, operand entries
+        // gathered with the op folded into the LDS addressing
+        const int ntiles = (ccnt + P - 1) / P;
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int mi = tile * P + L.sel;
+            LaneMat<T, TI> mt[1];
+            mt[0].valid = mi < ccnt;
+            mt[0].m = m;
+            mt[0].n = n;
+            mt[0].k = k;
+            mt[0].lda = ACONT ? k : m;
+            mt[0].ldb = BCONT ? k : n;
+            mt[0].ldc = m;
+            mt[0].A = lA + mi * eA;
+            mt[0].B = lB + mi * eB;
+            mt[0].C = lC + mi * eC;
+            mt[0].scale = 1.0f;
+            if (a.scaleA && mt[0].valid) mt[0].scale = a.scaleA[r * G + mi] * a.scaleB[r * G + mi];
+            tile_group<T, TI, MODE, D, 1, ACONT, BCONT>(mt, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
         }
         wave_lds_sync();
-
-        // C span LDS -> HBM, every byte of the span written once
-        const int FCo = cur.bytesC >> 4;
+        // C span LDS -> HBM (clamped, overlapping last chunk; every byte of the span written)
+        {
+            const int FCo = (cSC + 15) >> 4;
+            const int nt = (FCo + 63) >> 6;
 #pragma unroll
-        for (int t = 0; t < MAXCH; ++t) {
-            const int qq = lane + 64 * t;
-            if (qq < FCo) {
-                const u32x4 v = *reinterpret_cast<const u32x4*>(lds + offC + 16 * qq);
-                __builtin_memcpy(reinterpret_cast<unsigned int*>(cur.gC + 16 * qq), &v, 16);
+            for (int t = 0; t < MAXCH; ++t) {
+                if (t < nt) {
+                    int q = lane + 64 * t;
+                    q = q < FCo ? q : FCo - 1;
+                    const int off = (16 * q + 16 <= cSC) ? 16 * q : cSC - 16;
+                    const u32x4 v = *reinterpret_cast<const u32x4a4*>(lds + offC + off);
+                    *reinterpret_cast<u32x4a4*>(cgC + off) = v;
+                }
             }
         }
-        const int tw = (cur.bytesC & 15) >> 2;
-        if (lane < tw)
-            reinterpret_cast<unsigned int*>(cur.gC + 16 * FCo)[lane] =
-                *reinterpret_cast<const unsigned int*>(lds + offC + 16 * FCo + 4 * lane);
         wave_lds_sync();
-        cur = nxt;
     }
+#undef SBG_CHUNK
+#undef SBG_RUN_SPANS
 }
 
-// Matrices per step for the staged kernel, or 0 when one matrix's spans do
-// not fit the wave's LDS slice.
-template <typename T>
+// Matrices per wave step of the staged kernel, or 0 when it does not apply:
+// the run's spans must fit the wave's LDS slice, be at least 16 bytes and
+// consist of whole 4-byte words (for the last, possibly shorter run too).
+template <typename T, typename TI>
 inline int staged_run_length(int m, int n, int k, int64_t batch, int min_waves)
 {
-    const int per = (m * k + k * n + m * n) * (int)sizeof(T);
-    const int room = StagedCfg<T>::LDSW - 32;   // two 16-byte alignment pads
-    if (per <= 0 || per > room) return 0;
-    int G = room / per;
+    if (m < 1 || n < 1 || k < 1 || batch < 1) return 0;
+    const int64_t ei = (int64_t)sizeof(TI), ec = (int64_t)sizeof(T);
+    const int64_t per = (int64_t)(m * k + k * n) * ei + (int64_t)m * n * ec;
+    const int64_t room = StagedCfg<T>::LDSW - 32;   // two 16-byte alignment pads
+    if (per > room) return 0;
+    int64_t G = room / per;
     if (G > 256) G = 256;
     // enough runs to keep min_waves waves busy
     const int64_t fair = (batch + min_waves - 1) / min_waves;
-    if (fair < G) G = fair < 1 ? 1 : (int)fair;
-    // whole tiles per run where possible
-    int mx = m > n ? m : n;
-    mx = mx > k ? mx : k;
-    const int P = mx <= 4 ? 4 : (mx <= 8 ? 2 : 1);
-    if (G >= P) G -= G % P;
-    return G;
+    if (fair < G) G = fair < 1 ? 1 : fair;
+    // whole tiles per run, and whole 4-byte words for narrow inputs
+    const int64_t P = 16 / size_class(m, n, k);
+    const int64_t step = (ei < 4 && P < 4) ? 4 : P;
+    if (G >= step) G -= G % step;
+    else if (step * per <= room) G = step;
+    if (G > batch) G = batch;
+    const int64_t last = batch - ((batch - 1) / G) * G;   // matrices in the last run
+    for (const int64_t c : {G, last}) {
+        if (c * m * k * ei < 16 || c * k * n * ei < 16 || c * m * n * ec < 16) return 0;
+        if ((c * m * k * ei) % 4 || (c * k * n * ei) % 4) return 0;
+    }
+    return (int)G;
 }
 
-template <typename T, int D, bool ACONT, bool BCONT>
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream)
 {
-    auto kern = gemm_staged_kernel<T, D, ACONT, BCONT>;
-    const int64_t steps = (a.batch + a.G - 1) / a.G;
-    const int64_t grid = persistent_grid(kern, steps, a);
+    auto kern = gemm_staged_kernel<T, TI, MODE, D, ACONT, BCONT>;
+    const int64_t runs = (a.batch + a.G - 1) / a.G;
+    const int64_t grid = persistent_grid(kern, runs, a);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

@@ -192,14 +192,99 @@ struct Scalars {
     bool a0, b0;
 };
 
-// U tiles of one wavefront: loads of all U tiles first, then the MFMA steps
-// and the epilogues.  mats[u] describes the matrix this lane serves in tile u.
-// MODE 0: plain; MODE 1: BF16x3 (each binary32 operand split into bf16
-// hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
-template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT>
-__device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
-                                           const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
-                                           float b_conj)
+// Raw operand registers of U tiles (stored format, not yet decoded), so that
+// the loads of one group can be in flight while another group computes.
+template <typename T, typename TI, int D, int U>
+struct TileRegs {
+    TI va[U][D / 4];
+    TI vb[U][D / 4];
+    T cin[U][4];
+};
+
+// Issue the loads of U tiles: op(A) row ij and op(B) column ij of the lane's
+// matrix at k-indices kk0 .. kk0+KB-1, and the lane's C entries when
+// beta != 0.  Nothing here waits for the data.
+template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT>
+__device__ __forceinline__ void tile_load(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+                                          bool a0, bool b0, TileRegs<T, TI, D, U>& t)
+{
+    using R = typename Tr<T>::R;
+    using M = Mfma<R>;
+    constexpr int KB = D / 4;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const LaneMat<T, TI>& mt = mats[u];
+        const bool row_ok = L.ij < mt.m;
+        const bool col_ok = L.ij < mt.n;
+        const bool kfull = L.kk0 + KB <= mt.k;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            t.va[u][kb] = TI{};
+            t.vb[u][kb] = TI{};
+        }
+        const bool live = mt.valid && !a0;
+        if (live && row_ok) {
+            if (ACONT) {
+                const TI* src = mt.A + L.ij * mt.lda + L.kk0;
+                if (kfull) {
+                    vload<TI, KB>(t.va[u], src);
+                } else {
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb)
+                        if (L.kk0 + kb < mt.k) t.va[u][kb] = src[kb];
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (L.kk0 + kb < mt.k) t.va[u][kb] = mt.A[L.ij + (L.kk0 + kb) * mt.lda];
+            }
+        }
+        if (live && col_ok) {
+            if (BCONT) {
+                const TI* src = mt.B + L.ij * mt.ldb + L.kk0;
+                if (kfull) {
+                    vload<TI, KB>(t.vb[u], src);
+                } else {
+#pragma unroll
+                    for (int kb = 0; kb < KB; ++kb)
+                        if (L.kk0 + kb < mt.k) t.vb[u][kb] = src[kb];
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (L.kk0 + kb < mt.k) t.vb[u][kb] = mt.B[L.ij + (L.kk0 + kb) * mt.ldb];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) t.cin[u][r] = make_val<T>(R(0), R(0));
+        if (!b0 && mt.valid) {
+            if (M::swap) {
+                if (row_ok) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (L.keep[r] && L.orow[r] < mt.n) t.cin[u][r] = mt.C[L.ij + L.orow[r] * mt.ldc];
+                }
+            } else if (col_ok) {
+                const T* cb = mt.C + L.ij * mt.ldc;
+                if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
+                    vload<T, 4>(t.cin[u], cb + L.orow[0]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (L.keep[r] && L.orow[r] < mt.m) t.cin[u][r] = cb[L.orow[r]];
+                }
+            }
+        }
+    }
+}
+
+// Decode, multiply (MFMA steps) and write back U tiles whose loads were
+// issued by tile_load.  MODE 0: plain; MODE 1: BF16x3 (each binary32 operand
+// split into bf16 hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
+template <typename T, typename TI, int MODE, int D, int U>
+__device__ __forceinline__ void tile_finish(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+                                            const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
+                                            float b_conj, const TileRegs<T, TI, D, U>& t)
 {
     using R = typename Tr<T>::R;
     using M = Mfma<R>;
@@ -208,128 +293,51 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
     constexpr int KB = D / 4;
     const R ar_ = re_of<T>(alpha), ai_ = im_of<T>(alpha);
     const R br_ = re_of<T>(beta), bi_ = im_of<T>(beta);
-
-    R xa_r[U][KB], xa_i[U][KB], xb_r[U][KB], xb_i[U][KB];
-    T cin[U][4];
-    bool crun[U];
-
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const LaneMat<T, TI>& mt = mats[u];
         const bool row_ok = L.ij < mt.m;
         const bool col_ok = L.ij < mt.n;
-        const bool kfull = L.kk0 + KB <= mt.k;
-        TI va[KB], vb[KB];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            va[kb] = TI{};
-            vb[kb] = TI{};
-        }
         const bool live = mt.valid && !a0;
-        // op(A) row ij, k-indices kk0 .. kk0+KB-1
-        if (live && row_ok) {
-            if (ACONT) {
-                const TI* src = mt.A + L.ij * mt.lda + L.kk0;
-                if (kfull) {
-                    vload<TI, KB>(va, src);
-                } else {
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb)
-                        if (L.kk0 + kb < mt.k) va[kb] = src[kb];
-                }
-            } else {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb)
-                    if (L.kk0 + kb < mt.k) va[kb] = mt.A[L.ij + (L.kk0 + kb) * mt.lda];
-            }
-        }
-        // op(B) column ij, k-indices kk0 .. kk0+KB-1
-        if (live && col_ok) {
-            if (BCONT) {
-                const TI* src = mt.B + L.ij * mt.ldb + L.kk0;
-                if (kfull) {
-                    vload<TI, KB>(vb, src);
-                } else {
-#pragma unroll
-                    for (int kb = 0; kb < KB; ++kb)
-                        if (L.kk0 + kb < mt.k) vb[kb] = src[kb];
-                }
-            } else {
-#pragma unroll
-                for (int kb = 0; kb < KB; ++kb)
-                    if (L.kk0 + kb < mt.k) vb[kb] = mt.B[L.ij + (L.kk0 + kb) * mt.ldb];
-            }
-        }
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            // masked entries stay exact zeros (never a NaN from memory)
-            const bool oka = live && row_ok && (L.kk0 + kb) < mt.k;
-            const bool okb = live && col_ok && (L.kk0 + kb) < mt.k;
-            const T da = oka ? dec(va[kb]) : make_val<T>(R(0), R(0));
-            const T db = okb ? dec(vb[kb]) : make_val<T>(R(0), R(0));
-            xa_r[u][kb] = re_of<T>(da);
-            xb_r[u][kb] = re_of<T>(db);
-            xa_i[u][kb] = CPLX ? im_of<T>(da) * (R)a_conj : R(0);
-            xb_i[u][kb] = CPLX ? im_of<T>(db) * (R)b_conj : R(0);
-        }
-        // C input (only when beta != 0)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cin[u][r] = make_val<T>(R(0), R(0));
-        crun[u] = M::rows_contig && L.keep[0] && col_ok && (L.orow[0] + 3) < mt.m;
-        if (!b0 && mt.valid) {
-            if (M::swap) {
-                if (row_ok) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (L.keep[r] && L.orow[r] < mt.n) cin[u][r] = mt.C[L.ij + L.orow[r] * mt.ldc];
-                }
-            } else if (col_ok) {
-                const T* cb = mt.C + L.ij * mt.ldc;
-                if (crun[u]) {
-                    vload<T, 4>(cin[u], cb + L.orow[0]);
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (L.keep[r] && L.orow[r] < mt.m) cin[u][r] = cb[L.orow[r]];
-                }
-            }
-        }
-    }
-
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const LaneMat<T, TI>& mt = mats[u];
         acc_t acc_r = {0, 0, 0, 0};
         acc_t acc_i = {0, 0, 0, 0};
         if (!a0) {
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
+                // masked entries stay exact zeros (never a NaN from memory)
+                const bool oka = live && row_ok && (L.kk0 + kb) < mt.k;
+                const bool okb = live && col_ok && (L.kk0 + kb) < mt.k;
+                const T da = oka ? dec(t.va[u][kb]) : make_val<T>(R(0), R(0));
+                const T db = okb ? dec(t.vb[u][kb]) : make_val<T>(R(0), R(0));
+                const R xar = re_of<T>(da), xbr = re_of<T>(db);
+                const R xai = CPLX ? im_of<T>(da) * (R)a_conj : R(0);
+                const R xbi = CPLX ? im_of<T>(db) * (R)b_conj : R(0);
                 if (MODE == 1) {
-                    const R ah = (R)round_bf16((float)xa_r[u][kb]);
-                    const R al = (R)round_bf16((float)(xa_r[u][kb] - ah));
-                    const R bh = (R)round_bf16((float)xb_r[u][kb]);
-                    const R bl = (R)round_bf16((float)(xb_r[u][kb] - bh));
+                    const R ah = (R)round_bf16((float)xar);
+                    const R al = (R)round_bf16((float)(xar - ah));
+                    const R bh = (R)round_bf16((float)xbr);
+                    const R bl = (R)round_bf16((float)(xbr - bh));
                     acc_r = M::run(ah, bh, acc_r);
                     acc_r = M::run(ah, bl, acc_r);
                     acc_r = M::run(al, bh, acc_r);
                 } else if (M::swap) {
-                    acc_r = M::run(xb_r[u][kb], xa_r[u][kb], acc_r);
+                    acc_r = M::run(xbr, xar, acc_r);
                     if (CPLX) {
-                        acc_r = M::run(xb_i[u][kb], -xa_i[u][kb], acc_r);
-                        acc_i = M::run(xb_i[u][kb], xa_r[u][kb], acc_i);
-                        acc_i = M::run(xb_r[u][kb], xa_i[u][kb], acc_i);
+                        acc_r = M::run(xbi, -xai, acc_r);
+                        acc_i = M::run(xbi, xar, acc_i);
+                        acc_i = M::run(xbr, xai, acc_i);
                     }
                 } else {
-                    acc_r = M::run(xa_r[u][kb], xb_r[u][kb], acc_r);
+                    acc_r = M::run(xar, xbr, acc_r);
                     if (CPLX) {
-                        acc_r = M::run(-xa_i[u][kb], xb_i[u][kb], acc_r);
-                        acc_i = M::run(xa_r[u][kb], xb_i[u][kb], acc_i);
-                        acc_i = M::run(xa_i[u][kb], xb_r[u][kb], acc_i);
+                        acc_r = M::run(-xai, xbi, acc_r);
+                        acc_i = M::run(xar, xbi, acc_i);
+                        acc_i = M::run(xai, xbr, acc_i);
                     }
                 }
             }
         }
-        const bool lane_ok = M::swap ? (L.ij < mt.m) : (L.ij < mt.n);
+        const bool lane_ok = M::swap ? row_ok : col_ok;
         if (!(mt.valid && lane_ok)) continue;
         // scaled narrow inputs: alpha * sA * sB applied as (alpha sA sB) * acc
         R ar = ar_, ai = ai_;
@@ -337,14 +345,14 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
         T out[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            out[r] = axpby<T>(ar, ai, br_, bi_, a0, b0, acc_r[r], acc_i[r], cin[u][r]);
+            out[r] = axpby<T>(ar, ai, br_, bi_, a0, b0, acc_r[r], acc_i[r], t.cin[u][r]);
         if (M::swap) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 if (L.keep[r] && L.orow[r] < mt.n) mt.C[L.ij + L.orow[r] * mt.ldc] = out[r];
         } else {
             T* cb = mt.C + L.ij * mt.ldc;
-            if (crun[u]) {
+            if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
                 vstore<T, 4>(cb + L.orow[0], out);
             } else {
 #pragma unroll
@@ -353,6 +361,17 @@ __device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], cons
             }
         }
     }
+}
+
+// U tiles of one wavefront: all loads first, then the MFMA steps and epilogues.
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT>
+__device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+                                           const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
+                                           float b_conj)
+{
+    TileRegs<T, TI, D, U> t;
+    tile_load<T, TI, D, U, ACONT, BCONT>(mats, L, a0, b0, t);
+    tile_finish<T, TI, MODE, D, U>(mats, L, alpha, beta, a0, b0, a_conj, b_conj, t);
 }
 
 // Tiles per wave per step: keep roughly 3-6 KB of operand loads in flight per

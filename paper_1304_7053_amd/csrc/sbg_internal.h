@@ -51,16 +51,18 @@ struct GemmArgs {
 
 // Launch-shape knobs: work-groups per CU of the persistent grid, the XCD run
 // length and whether packed batches take the LDS-staged kernel.  Defaults
-// are the tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED and
-// SBG_TILE_BYTES override
+// are the tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
+// SBG_TILE_BYTES and SBG_PIPELINE override
 // them (read once per process) for tuning sweeps and A/B comparisons.
 struct Tuning {
     int wg_per_cu;
     int xcd_chunk;
     bool staged;      // use the LDS-staged kernel for packed strided batches
     int tile_bytes;   // bytes of loads and stores one wave keeps in flight per step
+    bool pipeline;    // issue the next group's loads before computing the current one
 };
 const Tuning& tuning();
+Tuning& tuning_mut();
 
 template <typename T>
 hipError_t launch_gemm(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream);

@@ -38,7 +38,7 @@ EXPORTS = [
     "sbg_status_string", "sbg_version", "sbg_describe_strided",
     "sbg_vbatched_workspace_size", "sbg_sgemm_vbatched", "sbg_dgemm_vbatched", "sbg_cgemm_vbatched",
     "sbg_zgemm_vbatched", "sbg_gemm_strided_batched_ex", "sbg_gemm_vbatched_ex",
-    "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched",
+    "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched", "sbg_set_tuning", "sbg_get_tuning",
 ]
 
 
@@ -96,6 +96,10 @@ def load():
     lib.sbg_quantize_e4m3_strided_batched.restype = c_int
     lib.sbg_quantize_e4m3_vbatched.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp, vp, i64, vp]
     lib.sbg_quantize_e4m3_vbatched.restype = c_int
+    lib.sbg_set_tuning.argtypes = [ctypes.c_char_p, c_int]
+    lib.sbg_set_tuning.restype = c_int
+    lib.sbg_get_tuning.argtypes = [ctypes.c_char_p]
+    lib.sbg_get_tuning.restype = c_int
     _lib = lib
     return lib
 
@@ -268,6 +272,39 @@ def describe_strided(prefix, transa, transb, m, n, k, lda, strideA, ldb, strideB
     rc = load().sbg_describe_strided(prefix.encode(), transa.encode(), transb.encode(), m, n, k, lda, strideA,
                                      ldb, strideB, ldc, strideC, batch, buf, 512)
     return buf.value.decode() if rc == 0 else None
+
+
+def set_tuning(key, value):
+    """Set a launch-tuning knob; returns the previous value."""
+    old = load().sbg_set_tuning(key.encode(), int(value))
+    if old < 0:
+        raise ValueError(f"bad tuning key or value: {key}={value}")
+    return old
+
+
+def get_tuning(key):
+    v = load().sbg_get_tuning(key.encode())
+    if v < 0:
+        raise ValueError(f"unknown tuning key {key}")
+    return v
+
+
+class tuned:
+    """Context manager setting tuning knobs for a block: with tuned(staged=1): ..."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+        self.old = {}
+
+    def __enter__(self):
+        for k, v in self.kw.items():
+            self.old[k] = set_tuning(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        for k, v in self.old.items():
+            set_tuning(k, v)
+        return False
 
 
 def last_invalid_arg():
