@@ -233,11 +233,14 @@ int sbg_version(void);
  * sweeps and A/B comparisons (not thread-safe against concurrent calls; set
  * them before launching).  Keys: "wg_per_cu" (persistent work-groups per CU,
  * 1..32), "xcd_chunk" (consecutive work units per XCD run, >= 1), "staged"
- * (0/1: packed strided batches through the LDS-staged kernel), "tile_bytes"
- * (per-wave bytes in flight that choose the tile unroll, 256..2^20),
+ * (packed strided batches through the LDS-staged kernel: 0 never, 1 always,
+ * 2 automatic = real types in the size-16 class except 16x16x16; default
+ * 2), "tile_bytes"
+ * and "tile_bytes16" (per-wave bytes in flight that choose the direct
+ * kernel's tile unroll for the size classes 4/8 and 16, 256..2^20),
  * "pipeline" (0/1: prefetch the next tile group in the direct kernel).
  * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
- * SBG_TILE_BYTES, SBG_PIPELINE set the initial values.
+ * SBG_TILE_BYTES, SBG_TILE_BYTES16, SBG_PIPELINE set the initial values.
  * sbg_set_tuning returns the previous value, or -1 for an unknown key or an
  * out-of-range value (nothing changed); sbg_get_tuning returns the value or -1. */
 int sbg_set_tuning(const char* key, int value);

@@ -37,7 +37,7 @@ int device_cu_count()
 Tuning& tuning_mut()
 {
     static Tuning t = [] {
-        Tuning v{8, 16, false, 8192, false};
+        Tuning v{8, 16, 2, 2048, 8192, false};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;
@@ -46,11 +46,18 @@ Tuning& tuning_mut()
             int x = std::atoi(e);
             if (x >= 1) v.xcd_chunk = x;
         }
-        if (const char* e = std::getenv("SBG_STAGED")) v.staged = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SBG_STAGED")) {
+            int x = std::atoi(e);
+            if (x >= 0 && x <= 2) v.staged = x;
+        }
         if (const char* e = std::getenv("SBG_PIPELINE")) v.pipeline = std::atoi(e) != 0;
         if (const char* e = std::getenv("SBG_TILE_BYTES")) {
             int x = std::atoi(e);
             if (x >= 256 && x <= (1 << 20)) v.tile_bytes = x;
+        }
+        if (const char* e = std::getenv("SBG_TILE_BYTES16")) {
+            int x = std::atoi(e);
+            if (x >= 256 && x <= (1 << 20)) v.tile_bytes16 = x;
         }
         return v;
     }();
@@ -598,12 +605,17 @@ int sbg_set_tuning(const char* key, int value)
         old = t.xcd_chunk;
         t.xcd_chunk = value;
     } else if (k == "staged") {
-        old = t.staged ? 1 : 0;
-        t.staged = value != 0;
+        if (value < 0 || value > 2) return -1;
+        old = t.staged;
+        t.staged = value;
     } else if (k == "tile_bytes") {
         if (value < 256 || value > (1 << 20)) return -1;
         old = t.tile_bytes;
         t.tile_bytes = value;
+    } else if (k == "tile_bytes16") {
+        if (value < 256 || value > (1 << 20)) return -1;
+        old = t.tile_bytes16;
+        t.tile_bytes16 = value;
     } else if (k == "pipeline") {
         old = t.pipeline ? 1 : 0;
         t.pipeline = value != 0;
@@ -620,8 +632,9 @@ int sbg_get_tuning(const char* key)
     const std::string k(key);
     if (k == "wg_per_cu") return t.wg_per_cu;
     if (k == "xcd_chunk") return t.xcd_chunk;
-    if (k == "staged") return t.staged ? 1 : 0;
+    if (k == "staged") return t.staged;
     if (k == "tile_bytes") return t.tile_bytes;
+    if (k == "tile_bytes16") return t.tile_bytes16;
     if (k == "pipeline") return t.pipeline ? 1 : 0;
     return -1;
 }

@@ -4,20 +4,22 @@
 //
 // In a packed batch a run of G consecutive matrices is one contiguous span of
 // each operand.  Each wavefront owns an LDS slice and processes runs:
-//   1. spans -> registers: lane i loads 16-byte chunks i, i+64, ... of the
-//      A, B (and, when beta != 0, C) spans as one flat chunk list.  Every load
-//      is unconditional: a chunk index past the end is clamped to the last
-//      chunk, and the last chunk of a span starts 16 bytes before the span's
-//      end (overlapping its neighbour), so no access leaves the span and no
-//      load sits behind a lane mask;
-//   2. registers -> LDS; the next run's chunk loads are issued right away
-//      and stay in flight while this run computes;
+//   1. spans -> registers: the whole 16-byte chunks of the A, B (and, when
+//      beta != 0, C) spans form one flat list; lane i loads chunks i, i+64,
+//      ...  A span whose length is not a multiple of 16 also has a tail: the
+//      16 bytes ending at the span's end (overlapping the last whole chunk),
+//      loaded by one lane.  No access leaves a span;
+//   2. registers -> LDS at the chunks' own offsets (16-byte aligned, so one
+//      128-bit LDS write each; the tails are written as 32-bit words); the
+//      next run's loads are issued right away and stay in flight while this
+//      run computes;
 //   3. LDS -> MFMA operands (the block-diagonal packing of the direct kernel:
 //      16/D matrices of size class D per 16x16x16 product), results written
 //      back into the C span in LDS;
-//   4. C span LDS -> HBM with the same clamped 16-byte chunks.
-// Whatever m, n, k are, every global access of a wave is a 1 KB contiguous
-// stream; small matrices move as many bytes per wave step as large ones.
+//   4. C span LDS -> HBM: whole chunks plus the overlapping tail.
+// Whatever m, n, k are, every global access of a wave is part of a 1 KB
+// contiguous stream; small matrices move as many bytes per wave step as
+// large ones.
 #pragma once
 
 #include "gemm_direct.h"
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
 {
     using R = typename Tr<T>::R;
     using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
-    // 16-byte vector at 4-byte alignment (chunk boundaries follow the spans)
+    // 16-byte vector at 4-byte alignment (global chunk addresses follow the spans)
     typedef unsigned int u32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
     constexpr int P = 16 / D;
     constexpr int LDSW = StagedCfg<T>::LDSW;
@@ -72,21 +74,20 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
     const unsigned char* gB0 = static_cast<const unsigned char*>(a.B);
     unsigned char* gC0 = reinterpret_cast<unsigned char*>(a.C);
 
-    // Spans of run r (the last run may be shorter; every span is >= 16 bytes
-    // of whole words, which the host guarantees): byte sizes SA, SB, SCin
-    // (loaded) and SC (stored), chunk counts FX = ceil(SX / 16).
     // the run index is wave-uniform: keep it (and all span arithmetic) scalar
     const int64_t r0 = xcd_wave_index(a.xcd_chunk);
     int64_t r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0 >> 32)) << 32) |
                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r0 & 0xFFFFFFFF));
     if (r >= nruns) return;
 
-    u32x4 buf[MAXCH];
+    // Spans of run RR (the last run may be shorter; every span is >= 16 bytes
+    // of whole 4-byte words, which the host guarantees): byte sizes SA, SB,
+    // SCin (loaded) and SC (stored), whole-chunk counts FA, FB and the flat
+    // list length FT.  All wave-uniform.
     int cnt = 0, SA = 0, SB = 0, SC = 0, SCin = 0, FA = 0, FB = 0, FT = 0;
     const unsigned char* gA = nullptr;
     const unsigned char* gB = nullptr;
     unsigned char* gC = nullptr;
-
 #define SBG_RUN_SPANS(RR)                                                           \
     {                                                                               \
         const int64_t p0 = (RR) * G;                                                \
@@ -98,73 +99,106 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
         SB = a0 ? 0 : cnt * eB * EI;                                                \
         SC = cnt * eC * EC;                                                         \
         SCin = b0 ? 0 : SC;                                                         \
-        FA = (SA + 15) >> 4;                                                        \
-        FB = (SB + 15) >> 4;                                                        \
-        FT = FA + FB + ((SCin + 15) >> 4);                                          \
+        FA = SA >> 4;                                                               \
+        FB = SB >> 4;                                                               \
+        FT = FA + FB + (SCin >> 4);                                                 \
     }
-    // chunk q (clamped to the list) of A | B | C: byte offset inside its span
-    // (the last chunk of a span ends at the span's end), source and LDS address
+    // whole chunk Q (< FT) of the flat list: global source and LDS destination
 #define SBG_CHUNK(Q, SRC, DST)                                                      \
     {                                                                               \
-        const int q_ = (Q) < FT ? (Q) : FT - 1;                                     \
-        const bool inA = q_ < FA;                                                   \
-        const bool inB = !inA && q_ < FA + FB;                                      \
-        const int loc = inA ? q_ : (inB ? q_ - FA : q_ - FA - FB);                  \
-        const int S_ = inA ? SA : (inB ? SB : SCin);                                \
-        const int off = (16 * loc + 16 <= S_) ? 16 * loc : S_ - 16;                 \
+        const bool inA = (Q) < FA;                                                  \
+        const bool inB = !inA && (Q) < FA + FB;                                     \
+        const int off = 16 * (inA ? (Q) : (inB ? (Q) - FA : (Q) - FA - FB));        \
         SRC = (inA ? gA : (inB ? gB : (const unsigned char*)gC)) + off;             \
         DST = (inA ? 0 : (inB ? offB : offC)) + off;                                \
     }
-
-    // The chunk loops below run MAXCH times unconditionally: indices past
-    // the list re-read (and re-write to LDS) the clamped last chunk, so the
-    // loads carry no branches and the compiler counts them exactly.
-    // With alpha == 0 and beta == 0 nothing is loaded (FT == 0): the chunk
-    // loops are skipped, since a clamped index would otherwise be -1.
-    SBG_RUN_SPANS(r)
-    if (FT > 0) {
-#pragma unroll
-        for (int t = 0; t < MAXCH; ++t) {
-            const unsigned char* src;
-            int dst;
-            SBG_CHUNK(lane + 64 * t, src, dst)
-            (void)dst;
-            buf[t] = *reinterpret_cast<const u32x4a4*>(src);
-        }
+    // tail of span J (0 A, 1 B, 2 C): the 16 bytes ending at the span's end,
+    // needed when the span is not a multiple of 16 bytes (HAS)
+#define SBG_TAIL(J, SRC, DST, HAS)                                                  \
+    {                                                                               \
+        const int S_ = (J) == 0 ? SA : ((J) == 1 ? SB : SCin);                      \
+        SRC = ((J) == 0 ? gA : ((J) == 1 ? gB : (const unsigned char*)gC)) + (S_ - 16); \
+        DST = ((J) == 0 ? 0 : ((J) == 1 ? offB : offC)) + (S_ - 16);                \
+        HAS = (S_ & 15) != 0;                                                       \
     }
+#define SBG_ISSUE()                                                                 \
+    {                                                                               \
+        const int nt_ = (FT + 63) >> 6;                                             \
+        _Pragma("unroll") for (int t = 0; t < MAXCH; ++t) {                         \
+            if (t < nt_) {                                                          \
+                const int q = lane + 64 * t;                                        \
+                if (q < FT) {                                                       \
+                    const unsigned char* src;                                       \
+                    int dst;                                                        \
+                    SBG_CHUNK(q, src, dst)                                          \
+                    (void)dst;                                                      \
+                    buf[t] = *reinterpret_cast<const u32x4a4*>(src);                \
+                }                                                                   \
+            }                                                                       \
+        }                                                                           \
+        if (lane < 3) {                                                             \
+            const unsigned char* src;                                               \
+            int dst;                                                                \
+            bool has;                                                               \
+            SBG_TAIL(lane, src, dst, has)                                           \
+            (void)dst;                                                              \
+            /* without a tail the lane re-reads the head of the C span (never   */ \
+            /* empty), so the load is issued on every run                       */ \
+            tbuf = *reinterpret_cast<const u32x4a4*>(has ? src : (const unsigned char*)gC); \
+        }                                                                           \
+    }
+#define SBG_COMMIT()                                                                \
+    {                                                                               \
+        const int nt_ = (FT + 63) >> 6;                                             \
+        _Pragma("unroll") for (int t = 0; t < MAXCH; ++t) {                         \
+            if (t < nt_) {                                                          \
+                const int q = lane + 64 * t;                                        \
+                if (q < FT) {                                                       \
+                    const unsigned char* src;                                       \
+                    int dst;                                                        \
+                    SBG_CHUNK(q, src, dst)                                          \
+                    (void)src;                                                      \
+                    *reinterpret_cast<u32x4*>(lds + dst) = buf[t];                  \
+                }                                                                   \
+            }                                                                       \
+        }                                                                           \
+        if (lane < 3) {                                                             \
+            const unsigned char* src;                                               \
+            int dst;                                                                \
+            bool has;                                                               \
+            SBG_TAIL(lane, src, dst, has)                                           \
+            (void)src;                                                              \
+            if (has) {                                                              \
+                unsigned int* w = reinterpret_cast<unsigned int*>(lds + dst);       \
+                w[0] = tbuf.x;                                                      \
+                w[1] = tbuf.y;                                                      \
+                w[2] = tbuf.z;                                                      \
+                w[3] = tbuf.w;                                                      \
+            }                                                                       \
+        }                                                                           \
+        /* the tail register is consumed here on every path, so the next       */ \
+        /* run's tail load never waits for this one                            */ \
+        __asm__ volatile("" ::"v"(tbuf));                                           \
+    }
+
+    u32x4 buf[MAXCH];
+    u32x4 tbuf = {0u, 0u, 0u, 0u};
+    SBG_RUN_SPANS(r)
+    SBG_ISSUE()
 
     const TI* lA = reinterpret_cast<const TI*>(lds);
     const TI* lB = reinterpret_cast<const TI*>(lds + offB);
     T* lC = reinterpret_cast<T*>(lds + offC);
 
     for (; r < nruns; r += W) {
-        // registers -> LDS for this run
-        if (FT > 0) {
-#pragma unroll
-            for (int t = 0; t < MAXCH; ++t) {
-                const unsigned char* src;
-                int dst;
-                SBG_CHUNK(lane + 64 * t, src, dst)
-                (void)src;
-                *reinterpret_cast<u32x4a4*>(lds + dst) = buf[t];
-            }
-        }
+        SBG_COMMIT()
         wave_lds_sync();
         const int ccnt = cnt, cSC = SC;
         unsigned char* cgC = gC;
         // next run's chunks: in flight while this run computes
         if (r + W < nruns) {
             SBG_RUN_SPANS(r + W)
-            if (FT > 0) {
-#pragma unroll
-                for (int t = 0; t < MAXCH; ++t) {
-                    const unsigned char* src;
-                    int dst;
-                    SBG_CHUNK(lane + 64 * t, src, dst)
-                    (void)dst;
-                    buf[t] = *reinterpret_cast<const u32x4a4*>(src);
-                }
-            }
+            SBG_ISSUE()
         }
         // tiles of the run from LDS: each lane's matrix mi, operand entries
         // gathered with the op folded into the LDS addressing
@@ -182,28 +216,35 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
             mt[0].A = lA + mi * eA;
             mt[0].B = lB + mi * eB;
             mt[0].C = lC + mi * eC;
-            mt[0].scale = 1.0f;
-            if (a.scaleA && mt[0].valid) mt[0].scale = a.scaleA[r * G + mi] * a.scaleB[r * G + mi];
+            mt[0].scale = 1.0f;   // per-matrix scales never take this kernel
             tile_group<T, TI, MODE, D, 1, ACONT, BCONT>(mt, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
         }
         wave_lds_sync();
-        // C span LDS -> HBM (clamped, overlapping last chunk; every byte of the span written)
+        // C span LDS -> HBM: whole chunks, then the overlapping tail
         {
-            const int FCo = (cSC + 15) >> 4;
-            const int nt = (FCo + 63) >> 6;
+            const int FC = cSC >> 4;
+            const int nt = (FC + 63) >> 6;
 #pragma unroll
             for (int t = 0; t < MAXCH; ++t) {
                 if (t < nt) {
-                    int q = lane + 64 * t;
-                    q = q < FCo ? q : FCo - 1;
-                    const int off = (16 * q + 16 <= cSC) ? 16 * q : cSC - 16;
-                    const u32x4 v = *reinterpret_cast<const u32x4a4*>(lds + offC + off);
-                    *reinterpret_cast<u32x4a4*>(cgC + off) = v;
+                    const int q = lane + 64 * t;
+                    if (q < FC) {
+                        const u32x4 v = *reinterpret_cast<const u32x4*>(lds + offC + 16 * q);
+                        *reinterpret_cast<u32x4a4*>(cgC + 16 * q) = v;
+                    }
                 }
+            }
+            if (lane == 0 && (cSC & 15)) {
+                const unsigned int* w = reinterpret_cast<const unsigned int*>(lds + offC + cSC - 16);
+                const u32x4 v = {w[0], w[1], w[2], w[3]};
+                *reinterpret_cast<u32x4a4*>(cgC + cSC - 16) = v;
             }
         }
         wave_lds_sync();
     }
+#undef SBG_ISSUE
+#undef SBG_COMMIT
+#undef SBG_TAIL
 #undef SBG_CHUNK
 #undef SBG_RUN_SPANS
 }

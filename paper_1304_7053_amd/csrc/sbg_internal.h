@@ -50,16 +50,18 @@ struct GemmArgs {
 };
 
 // Launch-shape knobs: work-groups per CU of the persistent grid, the XCD run
-// length and whether packed batches take the LDS-staged kernel.  Defaults
-// are the tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
-// SBG_TILE_BYTES and SBG_PIPELINE override
-// them (read once per process) for tuning sweeps and A/B comparisons.
+// length, which packed batches take the LDS-staged kernel and the per-wave
+// byte budgets that choose the direct kernel's tile unroll.  Defaults are the
+// tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED, SBG_TILE_BYTES,
+// SBG_TILE_BYTES16 and SBG_PIPELINE override them (read once per process) for
+// tuning sweeps and A/B comparisons.
 struct Tuning {
     int wg_per_cu;
     int xcd_chunk;
-    bool staged;      // use the LDS-staged kernel for packed strided batches
-    int tile_bytes;   // bytes of loads and stores one wave keeps in flight per step
-    bool pipeline;    // issue the next group's loads before computing the current one
+    int staged;        // 0 never, 1 every packed strided batch, 2 the 16 class except 16x16x16
+    int tile_bytes;    // per-wave bytes in flight per step, size classes 4 and 8
+    int tile_bytes16;  // the same for size class 16
+    bool pipeline;     // issue the next group's loads before computing the current one
 };
 const Tuning& tuning();
 Tuning& tuning_mut();

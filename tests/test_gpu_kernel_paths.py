@@ -17,8 +17,8 @@ pytestmark = pytest.mark.gpu
 PATHS = {
     "staged": dict(staged=1, pipeline=0),
     "pipelined": dict(staged=0, pipeline=1),
-    "unroll1": dict(staged=0, pipeline=0, tile_bytes=256),
-    "unrollmax": dict(staged=0, pipeline=0, tile_bytes=1 << 20),
+    "unroll1": dict(staged=0, pipeline=0, tile_bytes=256, tile_bytes16=256),
+    "unrollmax": dict(staged=0, pipeline=0, tile_bytes=1 << 20, tile_bytes16=1 << 20),
     "onewg": dict(staged=0, pipeline=0, wg_per_cu=1, xcd_chunk=1),
 }
 
