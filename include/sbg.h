@@ -234,10 +234,11 @@ int sbg_version(void);
  * them before launching).  Keys: "wg_per_cu" (persistent work-groups per CU,
  * 1..32), "xcd_chunk" (consecutive work units per XCD run, >= 1), "staged"
  * (packed strided batches through the LDS-staged kernel: 0 never, 1 always,
- * 2 automatic = real types in the size-16 class except 16x16x16; default
- * 2), "tile_bytes"
+ * 2 automatic = real types in the size-16 class except 16x16x16, for
+ * 8-byte inputs only up to 11 rows/columns; default 2), "tile_bytes"
  * and "tile_bytes16" (per-wave bytes in flight that choose the direct
- * kernel's tile unroll for the size classes 4/8 and 16, 256..2^20),
+ * kernel's tile unroll for the size classes 4/8 and 16, 256..2^20; the
+ * class-16 budget is for 4-byte elements and scales with the element size),
  * "pipeline" (0/1: prefetch the next tile group in the direct kernel).
  * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
  * SBG_TILE_BYTES, SBG_TILE_BYTES16, SBG_PIPELINE set the initial values.

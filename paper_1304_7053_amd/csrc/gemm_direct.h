@@ -208,7 +208,9 @@ inline int choose_unroll(const GemmArgs<T>& a)
     const int64_t P = 16 / D;
     const int64_t tile = P * ((int64_t)(a.m * a.k + a.k * a.n) * (int64_t)sizeof(TI) +
                               2 * (int64_t)a.m * a.n * (int64_t)sizeof(T));
-    const int64_t target = D == 16 ? tuning().tile_bytes16 : tuning().tile_bytes;
+    // class 16: the budget is stated for 4-byte elements and grows with the
+    // element size (measured: U = 2 at n = 16 for f32 and f64 alike)
+    const int64_t target = D == 16 ? tuning().tile_bytes16 * (int64_t)sizeof(T) / 4 : tuning().tile_bytes;
     int U = 1;
     while (U * 2 <= UMax<T, D>::value && (U * 2) * tile <= target) U *= 2;
     return U;
@@ -279,14 +281,18 @@ inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
 {
     const int mode = tuning().staged;
     if (pointer_form || mode == 0 || !is_packed(a) || a.scaleA) return 0;
-    // automatic choice: the 16 class gathers partly filled 16x16 tiles, whose
-    // direct loads touch many cache lines per useful byte; staged spans are
-    // whole 1 KB streams.  Exactly 16x16x16 and the smaller classes load
-    // whole lines directly and stay on the direct kernel.
-    // Complex types stay direct: their four real products per step double the
-    // LDS gathers, and measured slower staged.
-    if (mode == 2 && (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16 || (a.m == 16 && a.n == 16 && a.k == 16)))
-        return 0;
+    // Automatic choice (measured): in the 16 class the direct kernel gathers
+    // partly filled 16x16 tiles whose loads touch many cache lines per useful
+    // byte, while staged spans are whole 1 KB streams -- staged wins for
+    // 4-byte inputs, and for 8-byte ones up to 11 rows/columns (longer f64
+    // rows fill their lines directly).  Exactly 16x16x16, the smaller classes
+    // and the complex types (four real products per step double the LDS
+    // gathers) stay on the direct kernel.
+    if (mode == 2) {
+        const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
+        if (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16 || (a.m == 16 && a.n == 16 && a.k == 16)) return 0;
+        if (sizeof(TI) >= 8 && mx > 11) return 0;
+    }
     return staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
 }
 

@@ -60,7 +60,7 @@ struct Tuning {
     int xcd_chunk;
     int staged;        // 0 never, 1 every packed strided batch, 2 the 16 class except 16x16x16
     int tile_bytes;    // per-wave bytes in flight per step, size classes 4 and 8
-    int tile_bytes16;  // the same for size class 16
+    int tile_bytes16;  // the same for size class 16, per 4-byte element size (scaled by sizeof(T) / 4)
     bool pipeline;     // issue the next group's loads before computing the current one
 };
 const Tuning& tuning();
