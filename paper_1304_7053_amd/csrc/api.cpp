@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,22 @@ int device_cu_count()
         cache[dev] = cus;
     }
     return cache[dev];
+}
+
+int resident_blocks_per_cu(const void* kernel)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(kernel);
+        if (it != cache.end()) return it->second;
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
+    std::lock_guard<std::mutex> lock(mu);
+    cache[kernel] = nb;
+    return nb;
 }
 
 Tuning& tuning_mut()

@@ -134,17 +134,13 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
     }
 }
 
-// Work-groups that fit on one CU at once (registers and LDS), cached per kernel.
+// Work-groups of 256 threads that fit on one CU at once (registers and LDS),
+// cached per kernel (the cache is keyed by the kernel's address: kernels of
+// one argument type share a C++ type, not an occupancy).
 template <typename K>
 inline int resident_per_cu(K kernel)
 {
-    static int cached = 0;
-    if (cached == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb <= 0) nb = 1;
-        cached = nb;
-    }
-    return cached;
+    return resident_blocks_per_cu(reinterpret_cast<const void*>(kernel));
 }
 
 // Persistent grid for `units` independent wave-sized work units: at most the

@@ -10,7 +10,8 @@
 //                     (a kernel, not a memset node, so graph replays are safe);
 //   2. bin_kernel     classifies every matrix by size class D in {4, 8, 16}
 //                     (max of m, n, k), appends its index to that class's list
-//                     with one atomic per wave and class, and counts matrices
+//                     with one atomic per work-group and class (indices keep
+//                     their order within a work-group), and counts matrices
 //                     whose sizes or leading dimensions are invalid (those are
 //                     skipped, C untouched);
 //   3. vbatched_kernel walks the tiles of the three lists (largest class
@@ -26,6 +27,7 @@
 namespace sbg {
 
 constexpr int VB_HEADER = 16;
+constexpr int VB_BIN_PER = 4;   // matrices per thread of the binning kernel
 
 inline size_t vbatched_workspace_bytes(int64_t batch)
 {
@@ -107,7 +109,7 @@ template <typename T, typename TI, int MODE, bool ACONT, bool BCONT>
 hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
 {
     hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
-    const int64_t nb = (a.batch + 255) / 256;
+    const int64_t nb = (a.batch + 256 * VB_BIN_PER - 1) / (256 * VB_BIN_PER);
     hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(256), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,
                        a.dldc, a.max_m, a.max_n, a.max_k, a.a_trans, a.b_trans, a.batch, a.ws);
     auto kern = gemm_vbatched_kernel<T, TI, MODE, ACONT, BCONT>;

@@ -66,6 +66,11 @@ struct Tuning {
 const Tuning& tuning();
 Tuning& tuning_mut();
 
+// Compute units of the current device, cached per device.
+int device_cu_count();
+// Resident 256-thread work-groups per CU of a kernel, cached per kernel.
+int resident_blocks_per_cu(const void* kernel);
+
 template <typename T>
 hipError_t launch_gemm(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream);
 
@@ -102,7 +107,5 @@ struct QuantArgs {
 };
 
 hipError_t launch_quant_e4m3(const QuantArgs& q, bool var, hipStream_t stream);
-
-int device_cu_count();
 
 }  // namespace sbg

@@ -10,41 +10,69 @@ __global__ void vb_zero_kernel(int* ws)
     if (threadIdx.x < VB_HEADER) ws[threadIdx.x] = 0;
 }
 
+// One work-group bins VB_BIN_PER * 256 consecutive matrices: per-wave ballots
+// count each class, the counts are prefix-summed in LDS (in matrix order),
+// and one global atomic per class and work-group reserves the group's range
+// of each list.  Within a work-group the lists keep the matrices' order.
 __global__ __launch_bounds__(256) void vb_bin_kernel(const int* dm, const int* dn, const int* dk, const int* dlda,
                                                      const int* dldb, const int* dldc, int max_m, int max_n,
                                                      int max_k, bool a_trans, bool b_trans, int64_t batch,
                                                      int* ws)
 {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    int cls = -1;
-    bool bad = false;
-    if (p < batch) {
-        const int m = dm[p], n = dn[p], k = dk[p];
-        const int rowsA = a_trans ? k : m;
-        const int rowsB = b_trans ? n : k;
-        bad = m < 0 || n < 0 || k < 0 || m > max_m || n > max_n || k > max_k ||
-              dlda[p] < (rowsA > 1 ? rowsA : 1) || dldb[p] < (rowsB > 1 ? rowsB : 1) ||
-              dldc[p] < (m > 1 ? m : 1);
-        if (!bad && m > 0 && n > 0) {
-            const int D = size_class(m, n, k);
-            cls = D == 4 ? 0 : (D == 8 ? 1 : 2);
-        }
-    }
-    // one atomic per wave and class; lanes take consecutive slots
+    __shared__ int cnt[VB_BIN_PER][4][4];   // [step][wave][class 0..2, invalid 3] -> exclusive prefix
+    __shared__ int base[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * (256 * VB_BIN_PER);
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int cls[VB_BIN_PER];
+    unsigned long long rank[VB_BIN_PER];   // this lane's position among its wave's lanes of the same class
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const unsigned long long mask = __ballot(cls == c);
-        if (mask == 0) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&ws[c], __popcll(mask));
-        base = __shfl(base, leader);
-        if (cls == c) ws[VB_HEADER + (int64_t)c * batch + base + __popcll(mask & below)] = (int)p;
+    for (int it = 0; it < VB_BIN_PER; ++it) {
+        const int64_t p = p0 + it * 256 + tid;
+        int c = -1;
+        bool bad = false;
+        if (p < batch) {
+            const int m = dm[p], n = dn[p], k = dk[p];
+            const int rowsA = a_trans ? k : m;
+            const int rowsB = b_trans ? n : k;
+            bad = m < 0 || n < 0 || k < 0 || m > max_m || n > max_n || k > max_k ||
+                  dlda[p] < (rowsA > 1 ? rowsA : 1) || dldb[p] < (rowsB > 1 ? rowsB : 1) ||
+                  dldc[p] < (m > 1 ? m : 1);
+            if (!bad && m > 0 && n > 0) {
+                const int D = size_class(m, n, k);
+                c = D == 4 ? 0 : (D == 8 ? 1 : 2);
+            }
+        }
+        cls[it] = c;
+        rank[it] = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const unsigned long long mask = __ballot(c == j);
+            if (c == j) rank[it] = __popcll(mask & below);
+            if (lane == 0) cnt[it][w][j] = __popcll(mask);
+        }
+        const unsigned long long badm = __ballot(bad);
+        if (lane == 0) cnt[it][w][3] = __popcll(badm);
     }
-    const unsigned long long badm = __ballot(bad);
-    if (badm && lane == __ffsll((long long)badm) - 1) atomicAdd(&ws[3], __popcll(badm));
+    __syncthreads();
+    if (tid < 4) {
+        int run = 0;
+        for (int it = 0; it < VB_BIN_PER; ++it)
+            for (int ww = 0; ww < 4; ++ww) {
+                const int x = cnt[it][ww][tid];
+                cnt[it][ww][tid] = run;
+                run += x;
+            }
+        base[tid] = run ? atomicAdd(&ws[tid], run) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < VB_BIN_PER; ++it) {
+        const int c = cls[it];
+        if (c >= 0)
+            ws[VB_HEADER + (int64_t)c * batch + base[c] + cnt[it][w][c] + (int)rank[it]] =
+                (int)(p0 + it * 256 + tid);
+    }
 }
 
 }  // namespace sbg
