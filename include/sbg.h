@@ -148,9 +148,10 @@ sbg_status_t sbg_zgemm_batched(char transa, char transb, int m, int n, int k,
  *     gives SBG_NOT_SUPPORTED).  A matrix whose sizes exceed them, are
  *     negative, or whose leading dimensions are too small is SKIPPED (its C is
  *     untouched) and counted in the int at word 3 of the workspace.
- *   workspace: caller-owned device memory of at least
- *     sbg_vbatched_workspace_size(batch_count) bytes; it is overwritten on
- *     every call, so concurrent calls need distinct workspaces.
+ *   workspace: caller-owned, 16-byte aligned device memory of at least
+ *     sbg_vbatched_workspace_size(batch_count) bytes (64 + 144 per matrix);
+ *     it is overwritten on every call, so concurrent calls need distinct
+ *     workspaces.
  * Positions: 1 transa, 2 transb, 3 d_m, 4 d_n, 5 d_k, 6 max_m, 7 max_n,
  * 8 max_k, 9 alpha, 10 Aarray, 11 d_lda, 12 Barray, 13 d_ldb, 14 beta,
  * 15 Carray, 16 d_ldc, 17 batch_count (<= 2^31 - 1), 18 workspace,

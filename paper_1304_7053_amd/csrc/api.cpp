@@ -309,7 +309,7 @@ sbg_status_t vb_run(char transa, char transb, const int* dm, const int* dn, cons
     if (nonempty && !Carr) return reject(pos.C);
     if (nonempty && !dldc) return reject(pos.ldc);
     if (batch < 0 || batch > 0x7FFFFFFF) return reject(pos.batch);
-    if (nonempty && !ws) return reject(pos.ws);
+    if (nonempty && (!ws || (reinterpret_cast<uintptr_t>(ws) & 15))) return reject(pos.ws);
     if (max_m > 16 || max_n > 16 || max_k > 16) return SBG_NOT_SUPPORTED;
     if (!nonempty) return SBG_OK;
     if (ws_bytes < vb_workspace_bytes(batch)) return SBG_WORKSPACE_TOO_SMALL;

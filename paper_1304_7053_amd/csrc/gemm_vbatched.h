@@ -9,39 +9,61 @@
 //   1. zero_kernel    clears the four counters of the caller's workspace
 //                     (a kernel, not a memset node, so graph replays are safe);
 //   2. bin_kernel     classifies every matrix by size class D in {4, 8, 16}
-//                     (max of m, n, k), appends its index to that class's list
-//                     with one atomic per work-group and class (indices keep
-//                     their order within a work-group), and counts matrices
-//                     whose sizes or leading dimensions are invalid (those are
-//                     skipped, C untouched);
+//                     (max of m, n, k) and appends a record of it -- its
+//                     three pointers, leading dimensions, packed sizes and
+//                     fp8 scale product -- to that class's list, with one
+//                     atomic per work-group and class (records keep their
+//                     order within a work-group); matrices whose sizes or
+//                     leading dimensions are invalid are counted and skipped
+//                     (C untouched);
 //   3. vbatched_kernel walks the tiles of the three lists (largest class
 //                     first) with the same tile routine as the uniform forms;
-//                     each lane reads its own matrix's sizes, so one tile may
-//                     pack matrices of different shapes within a class.
-// Workspace (int32 words): [0..2] class counts, [3] rejected matrices,
-// [16 .. 16 + 3 N) the three index lists of capacity N each.
+//                     each lane reads its own matrix's record, one contiguous
+//                     48-byte load, so operands are one dependent step away.
+// Workspace (16-byte aligned): int32 words [0..2] class counts, [3] rejected
+// matrices; from byte 64 the three record lists of capacity N each.
 #pragma once
 
 #include "gemm_direct.h"
 
 namespace sbg {
 
-constexpr int VB_HEADER = 16;
+constexpr int VB_HEADER_BYTES = 64;
 constexpr int VB_BIN_PER = 4;   // matrices per thread of the binning kernel
+
+// One binned matrix.
+struct alignas(16) VbRec {
+    const void* A;
+    const void* B;
+    void* C;
+    int lda, ldb, ldc;
+    int mnk;      // m | n << 8 | k << 16
+    float scale;  // sA * sB for scaled fp8 inputs, 1 otherwise
+    int pad;
+};
+static_assert(sizeof(VbRec) == 48, "record layout");
 
 inline size_t vbatched_workspace_bytes(int64_t batch)
 {
-    return (size_t)(VB_HEADER + 3 * (batch > 0 ? batch : 0)) * sizeof(int);
+    return (size_t)VB_HEADER_BYTES + 3 * (size_t)(batch > 0 ? batch : 0) * sizeof(VbRec);
+}
+
+__device__ __host__ inline const VbRec* vb_list(const int* ws, int64_t batch, int c)
+{
+    return reinterpret_cast<const VbRec*>(reinterpret_cast<const unsigned char*>(ws) + VB_HEADER_BYTES) +
+           (int64_t)c * batch;
 }
 
 __global__ void vb_zero_kernel(int* ws);
 __global__ __launch_bounds__(256) void vb_bin_kernel(const int* dm, const int* dn, const int* dk, const int* dlda,
-                                                     const int* dldb, const int* dldc, int max_m, int max_n,
-                                                     int max_k, bool a_trans, bool b_trans, int64_t batch,
-                                                     int* ws);
+                                                     const int* dldb, const int* dldc, const void* const* Aarr,
+                                                     const void* const* Barr, void* const* Carr,
+                                                     const float* scaleA, const float* scaleB, int max_m,
+                                                     int max_n, int max_k, bool a_trans, bool b_trans,
+                                                     int64_t batch, int* ws);
 
 template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
-__device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, int count, const int* list,
+__device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, int count, const VbRec* list,
                                            const T& alpha, const T& beta, bool a0, bool b0)
 {
     using R = typename Tr<T>::R;
@@ -61,19 +83,19 @@ __device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, in
         mt.C = nullptr;
         mt.scale = 1.0f;
         if (mt.valid) {
-            const int p = list[li];
-            mt.m = a.dm[p];
-            mt.n = a.dn[p];
-            mt.k = a.dk[p];
-            mt.lda = a.dlda[p];
-            mt.ldb = a.dldb[p];
-            mt.ldc = a.dldc[p];
+            const VbRec r = list[li];
+            mt.m = r.mnk & 0xFF;
+            mt.n = (r.mnk >> 8) & 0xFF;
+            mt.k = (r.mnk >> 16) & 0xFF;
+            mt.lda = r.lda;
+            mt.ldb = r.ldb;
+            mt.ldc = r.ldc;
             if (!a0) {
-                mt.A = static_cast<const TI*>(a.Aarr[p]);
-                mt.B = static_cast<const TI*>(a.Barr[p]);
+                mt.A = static_cast<const TI*>(r.A);
+                mt.B = static_cast<const TI*>(r.B);
             }
-            mt.C = a.Carr[p];
-            if (a.scaleA) mt.scale = a.scaleA[p] * a.scaleB[p];
+            mt.C = static_cast<T*>(r.C);
+            mt.scale = r.scale;
         }
     }
     tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
@@ -86,9 +108,9 @@ __global__ __launch_bounds__(256) void gemm_vbatched_kernel(const GemmArgs<T> a)
     load_scalars(a, alpha, beta);
     const bool a0 = is_zero(alpha), b0 = is_zero(beta);
     const int c4 = a.ws[0], c8 = a.ws[1], c16 = a.ws[2];
-    const int* l4 = a.ws + VB_HEADER;
-    const int* l8 = l4 + a.batch;
-    const int* l16 = l8 + a.batch;
+    const VbRec* l4 = vb_list(a.ws, a.batch, 0);
+    const VbRec* l8 = vb_list(a.ws, a.batch, 1);
+    const VbRec* l16 = vb_list(a.ws, a.batch, 2);
     constexpr int U4 = Unroll<T, 4>::value, U8 = Unroll<T, 8>::value, U16 = Unroll<T, 16>::value;
     const int64_t g16 = (c16 + U16 - 1) / U16;
     const int64_t g8 = ((c8 + 1) / 2 + U8 - 1) / U8;
@@ -111,7 +133,8 @@ hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
     hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
     const int64_t nb = (a.batch + 256 * VB_BIN_PER - 1) / (256 * VB_BIN_PER);
     hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(256), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,
-                       a.dldc, a.max_m, a.max_n, a.max_k, a.a_trans, a.b_trans, a.batch, a.ws);
+                       a.dldc, a.Aarr, a.Barr, reinterpret_cast<void* const*>(a.Carr), a.scaleA, a.scaleB,
+                       a.max_m, a.max_n, a.max_k, a.a_trans, a.b_trans, a.batch, a.ws);
     auto kern = gemm_vbatched_kernel<T, TI, MODE, ACONT, BCONT>;
     // the class counts are only known on the device: size the grid for the
     // case with the most work units (every matrix in the 16 class)

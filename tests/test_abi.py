@@ -156,3 +156,23 @@ def test_tuning_knobs_round_trip():
     with sbg.tuned(pipeline=1, tile_bytes=4096):
         assert sbg.get_tuning("pipeline") == 1 and sbg.get_tuning("tile_bytes") == 4096
     assert sbg.get_tuning("tile_bytes") == defaults["tile_bytes"] or "SBG_TILE_BYTES" in os.environ
+
+
+def test_vbatched_workspace_validation():
+    """The var-size workspace must be non-null, 16-byte aligned and large
+    enough; checked before anything is launched."""
+    L = sbg.load()
+    f = L.sbg_sgemm_vbatched
+    a = vp(scal("s", 1.0))
+    need = L.sbg_vbatched_workspace_size(10)
+    assert need == 64 + 3 * 10 * 48
+    P = ctypes.c_void_p
+    fake = P(1 << 20)  # never dereferenced: every call below fails validation
+    args = lambda ws, wsb: (ctypes.c_char(b"N"), ctypes.c_char(b"N"), fake, fake, fake, ctypes.c_int(8),  # noqa
+                            ctypes.c_int(8), ctypes.c_int(8), a, fake, fake, fake, fake, a, fake, fake,
+                            ctypes.c_int64(10), P(ws), ctypes.c_size_t(wsb), P(None))
+    assert f(*args(None, need)) == sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == 18
+    assert f(*args((1 << 20) + 8, need)) == sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == 18
+    assert f(*args(1 << 20, need - 1)) == sbg.SBG_WORKSPACE_TOO_SMALL
