@@ -235,8 +235,9 @@ int sbg_version(void);
  * them before launching).  Keys: "wg_per_cu" (persistent work-groups per CU,
  * 1..32), "xcd_chunk" (consecutive work units per XCD run, >= 1), "staged"
  * (packed strided batches through the LDS-staged kernel: 0 never, 1 always,
- * 2 automatic = real types in the size-16 class except 16x16x16, for
- * 8-byte inputs only up to 11 rows/columns; default 2), "tile_bytes"
+ * 2 automatic = real types in the size-16 class, for 4-byte inputs unless m
+ * and k are multiples of 4, for 8-byte inputs up to 11 rows/columns; default
+ * 2), "tile_bytes"
  * and "tile_bytes16" (per-wave bytes in flight that choose the direct
  * kernel's tile unroll for the size classes 4/8 and 16, 256..2^20; the
  * class-16 budget is for 4-byte elements and scales with the element size),

@@ -54,7 +54,7 @@ int resident_blocks_per_cu(const void* kernel)
 Tuning& tuning_mut()
 {
     static Tuning t = [] {
-        Tuning v{8, 16, 2, 2048, 8192, false};
+        Tuning v{4, 16, 2, 2048, 8192, false};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;

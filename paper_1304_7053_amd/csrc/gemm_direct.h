@@ -77,6 +77,9 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
             const int64_t p = ((grp * U + u) * P) + L.sel;
             LaneMat<T, TI>& mt = mats[u];
             mt.valid = p < a.batch;
+            // lanes past the batch carry the last matrix's pointers (their
+            // loads stay in bounds; nothing of theirs is stored)
+            const int64_t pe = mt.valid ? p : a.batch - 1;
             mt.m = a.m;
             mt.n = a.n;
             mt.k = a.k;
@@ -85,22 +88,21 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
             mt.ldc = a.ldc;
             mt.A = nullptr;
             mt.B = nullptr;
-            mt.C = nullptr;
             mt.scale = 1.0f;
-            if (mt.valid) {
-                if (PTR) {
-                    if (!a0) {
-                        mt.A = static_cast<const TI*>(a.Aarr[p]);
-                        mt.B = static_cast<const TI*>(a.Barr[p]);
-                    }
-                    mt.C = a.Carr[p];
-                } else {
-                    mt.A = static_cast<const TI*>(a.A) + p * a.strideA;
-                    mt.B = static_cast<const TI*>(a.B) + p * a.strideB;
-                    mt.C = a.C + p * a.strideC;
+            if (PTR) {
+                if (!a0) {
+                    mt.A = static_cast<const TI*>(a.Aarr[pe]);
+                    mt.B = static_cast<const TI*>(a.Barr[pe]);
                 }
-                if (a.scaleA) mt.scale = a.scaleA[p] * a.scaleB[p];
+                mt.C = a.Carr[pe];
+            } else {
+                if (!a0) {
+                    mt.A = static_cast<const TI*>(a.A) + pe * a.strideA;
+                    mt.B = static_cast<const TI*>(a.B) + pe * a.strideB;
+                }
+                mt.C = a.C + pe * a.strideC;
             }
+            if (a.scaleA) mt.scale = a.scaleA[pe] * a.scaleB[pe];
         }
     };
 
@@ -277,17 +279,17 @@ inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
 {
     const int mode = tuning().staged;
     if (pointer_form || mode == 0 || !is_packed(a) || a.scaleA) return 0;
-    // Automatic choice (measured): in the 16 class the direct kernel gathers
-    // partly filled 16x16 tiles whose loads touch many cache lines per useful
-    // byte, while staged spans are whole 1 KB streams -- staged wins for
-    // 4-byte inputs, and for 8-byte ones up to 11 rows/columns (longer f64
-    // rows fill their lines directly).  Exactly 16x16x16, the smaller classes
-    // and the complex types (four real products per step double the LDS
-    // gathers) stay on the direct kernel.
+    // Automatic choice (measured): in the 16 class the staged kernel wins
+    // when the direct kernel cannot use whole vectors -- for 4-byte inputs
+    // unless m and k are multiples of 4 (then the k-contiguous operand and C
+    // load as 16-byte vectors), for 8-byte inputs up to 11 rows/columns
+    // (longer f64 rows fill their cache lines directly).  The smaller
+    // classes and the complex types (four real products per step double the
+    // LDS gathers) stay on the direct kernel.
     if (mode == 2) {
         const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
-        if (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16 || (a.m == 16 && a.n == 16 && a.k == 16)) return 0;
-        if (sizeof(TI) >= 8 && mx > 11) return 0;
+        if (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16) return 0;
+        if (sizeof(TI) >= 8 ? mx > 11 : ((a.m & 3) == 0 && (a.k & 3) == 0)) return 0;
     }
     return staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
 }

@@ -204,9 +204,10 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
         // gathered with the op folded into the LDS addressing
         const int ntiles = (ccnt + P - 1) / P;
         for (int tile = 0; tile < ntiles; ++tile) {
-            const int mi = tile * P + L.sel;
+            const int mi0 = tile * P + L.sel;
             LaneMat<T, TI> mt[1];
-            mt[0].valid = mi < ccnt;
+            mt[0].valid = mi0 < ccnt;
+            const int mi = mt[0].valid ? mi0 : ccnt - 1;   // lanes past the run read its last matrix
             mt[0].m = m;
             mt[0].n = n;
             mt[0].k = k;

@@ -204,74 +204,76 @@ struct TileRegs {
 // Issue the loads of U tiles: op(A) row ij and op(B) column ij of the lane's
 // matrix at k-indices kk0 .. kk0+KB-1, and the lane's C entries when
 // beta != 0.  Nothing here waits for the data.
+//
+// The loads are branch-free: every lane of a live tile issues the same
+// loads, an entry outside its matrix reading the matrix's first element
+// instead (tile_finish masks it to zero, or never stores it), and nothing is
+// zero-filled here.  A register written under a lane mask while loads into it
+// are in flight for other lanes forces the compiler to wait for every load
+// of the wave; without masks the loads of all U tiles stay in flight
+// together.  The caller's pointers must be valid whenever the tile is live
+// (tiles past the batch carry a valid matrix's pointers with valid = false),
+// except A and B when alpha == 0 or k == 0 (then they are not read).
 template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT>
 __device__ __forceinline__ void tile_load(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                           bool a0, bool b0, TileRegs<T, TI, D, U>& t)
 {
-    using R = typename Tr<T>::R;
-    using M = Mfma<R>;
+    using M = Mfma<typename Tr<T>::R>;
     constexpr int KB = D / 4;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const LaneMat<T, TI>& mt = mats[u];
         const bool row_ok = L.ij < mt.m;
         const bool col_ok = L.ij < mt.n;
-        const bool kfull = L.kk0 + KB <= mt.k;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-            t.va[u][kb] = TI{};
-            t.vb[u][kb] = TI{};
-        }
-        const bool live = mt.valid && !a0;
-        if (live && row_ok) {
+        // vector loads of the k-contiguous operands when k is a multiple of
+        // the lane's k-run (each run then whole or past k), scalars otherwise
+        const bool kvec = (mt.k % KB) == 0;
+        if (!a0 && mt.k > 0) {
             if (ACONT) {
                 const TI* src = mt.A + L.ij * mt.lda + L.kk0;
-                if (kfull) {
-                    vload<TI, KB>(t.va[u], src);
+                if (kvec) {
+                    vload<TI, KB>(t.va[u], (row_ok && L.kk0 < mt.k) ? src : mt.A);
                 } else {
 #pragma unroll
                     for (int kb = 0; kb < KB; ++kb)
-                        if (L.kk0 + kb < mt.k) t.va[u][kb] = src[kb];
+                        t.va[u][kb] = *((row_ok && L.kk0 + kb < mt.k) ? src + kb : mt.A);
                 }
             } else {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb)
-                    if (L.kk0 + kb < mt.k) t.va[u][kb] = mt.A[L.ij + (L.kk0 + kb) * mt.lda];
+                    t.va[u][kb] = *((row_ok && L.kk0 + kb < mt.k) ? mt.A + L.ij + (L.kk0 + kb) * mt.lda : mt.A);
             }
-        }
-        if (live && col_ok) {
             if (BCONT) {
                 const TI* src = mt.B + L.ij * mt.ldb + L.kk0;
-                if (kfull) {
-                    vload<TI, KB>(t.vb[u], src);
+                if (kvec) {
+                    vload<TI, KB>(t.vb[u], (col_ok && L.kk0 < mt.k) ? src : mt.B);
                 } else {
 #pragma unroll
                     for (int kb = 0; kb < KB; ++kb)
-                        if (L.kk0 + kb < mt.k) t.vb[u][kb] = src[kb];
+                        t.vb[u][kb] = *((col_ok && L.kk0 + kb < mt.k) ? src + kb : mt.B);
                 }
             } else {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb)
-                    if (L.kk0 + kb < mt.k) t.vb[u][kb] = mt.B[L.ij + (L.kk0 + kb) * mt.ldb];
+                    t.vb[u][kb] = *((col_ok && L.kk0 + kb < mt.k) ? mt.B + L.ij + (L.kk0 + kb) * mt.ldb : mt.B);
             }
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) t.cin[u][r] = make_val<T>(R(0), R(0));
-        if (!b0 && mt.valid) {
+        if (!b0) {
             if (M::swap) {
-                if (row_ok) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (L.keep[r] && L.orow[r] < mt.n) t.cin[u][r] = mt.C[L.ij + L.orow[r] * mt.ldc];
-                }
-            } else if (col_ok) {
+                for (int r = 0; r < 4; ++r)
+                    t.cin[u][r] = *((row_ok && L.keep[r] && L.orow[r] < mt.n) ? mt.C + L.ij + L.orow[r] * mt.ldc
+                                                                                 : mt.C);
+            } else {
+                // rows 4g'..4g'+3 of the lane's column: a vector when m is a
+                // multiple of 4 (each lane's rows whole or past m)
                 const T* cb = mt.C + L.ij * mt.ldc;
-                if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
-                    vload<T, 4>(t.cin[u], cb + L.orow[0]);
+                if (M::rows_contig && (mt.m & 3) == 0) {
+                    vload<T, 4>(t.cin[u], (col_ok && L.keep[0] && L.orow[0] < mt.m) ? cb + L.orow[0] : mt.C);
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        if (L.keep[r] && L.orow[r] < mt.m) t.cin[u][r] = cb[L.orow[r]];
+                        t.cin[u][r] = *((col_ok && L.keep[r] && L.orow[r] < mt.m) ? cb + L.orow[r] : mt.C);
                 }
             }
         }
@@ -301,7 +303,12 @@ __device__ __forceinline__ void tile_finish(const LaneMat<T, TI> (&mats)[U], con
         const bool live = mt.valid && !a0;
         acc_t acc_r = {0, 0, 0, 0};
         acc_t acc_i = {0, 0, 0, 0};
-        if (!a0) {
+        // The MFMA chain runs whatever alpha is (with alpha == 0 every operand
+        // is masked to zero): a branch around it separates the last MFMA from
+        // the accumulator reads below by a block boundary, across which the
+        // required wait states were found missing (reads of the last
+        // accumulator row returned stale values).
+        {
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
                 // masked entries stay exact zeros (never a NaN from memory)

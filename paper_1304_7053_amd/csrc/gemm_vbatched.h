@@ -76,27 +76,22 @@ __device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, in
         const int64_t li = (grp * U + u) * P + L.sel;
         LaneMat<T, TI>& mt = mats[u];
         mt.valid = li < count;
-        mt.m = mt.n = mt.k = 0;
-        mt.lda = mt.ldb = mt.ldc = 1;
+        // lanes past the list carry its last matrix (loads in bounds, nothing stored)
+        const VbRec r = list[mt.valid ? li : count - 1];
+        mt.m = r.mnk & 0xFF;
+        mt.n = (r.mnk >> 8) & 0xFF;
+        mt.k = (r.mnk >> 16) & 0xFF;
+        mt.lda = r.lda;
+        mt.ldb = r.ldb;
+        mt.ldc = r.ldc;
         mt.A = nullptr;
         mt.B = nullptr;
-        mt.C = nullptr;
-        mt.scale = 1.0f;
-        if (mt.valid) {
-            const VbRec r = list[li];
-            mt.m = r.mnk & 0xFF;
-            mt.n = (r.mnk >> 8) & 0xFF;
-            mt.k = (r.mnk >> 16) & 0xFF;
-            mt.lda = r.lda;
-            mt.ldb = r.ldb;
-            mt.ldc = r.ldc;
-            if (!a0) {
-                mt.A = static_cast<const TI*>(r.A);
-                mt.B = static_cast<const TI*>(r.B);
-            }
-            mt.C = static_cast<T*>(r.C);
-            mt.scale = r.scale;
+        if (!a0) {
+            mt.A = static_cast<const TI*>(r.A);
+            mt.B = static_cast<const TI*>(r.B);
         }
+        mt.C = static_cast<T*>(r.C);
+        mt.scale = r.scale;
     }
     tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
 }

@@ -135,7 +135,7 @@ def test_tuning_knobs_round_trip():
     """Launch-tuning knobs: defaults, set returns the previous value, invalid
     keys and out-of-range values are rejected without changing anything."""
     lib = sbg.load()
-    defaults = {"wg_per_cu": 8, "xcd_chunk": 16, "staged": 2, "tile_bytes": 2048, "tile_bytes16": 8192,
+    defaults = {"wg_per_cu": 4, "xcd_chunk": 16, "staged": 2, "tile_bytes": 2048, "tile_bytes16": 8192,
                 "pipeline": 0}
     env = {"wg_per_cu": "SBG_WG_PER_CU", "xcd_chunk": "SBG_XCD_CHUNK", "staged": "SBG_STAGED",
            "tile_bytes": "SBG_TILE_BYTES", "tile_bytes16": "SBG_TILE_BYTES16", "pipeline": "SBG_PIPELINE"}
