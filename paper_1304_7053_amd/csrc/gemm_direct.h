@@ -71,11 +71,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
     const int64_t ngroups = (ntiles + U - 1) / U;
 
     // the matrices this lane serves in the U tiles of group grp
-    auto setup = [&](int64_t grp, LaneMat<T, TI> (&mats)[U]) {
+    auto setup = [&](int64_t grp, LaneMat<T, TI, 1> (&mats)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t p = ((grp * U + u) * P) + L.sel;
-            LaneMat<T, TI>& mt = mats[u];
+            LaneMat<T, TI, 1>& mt = mats[u];
             mt.valid = p < a.batch;
             // lanes past the batch carry the last matrix's pointers (their
             // loads stay in bounds; nothing of theirs is stored)
@@ -91,16 +91,16 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
             mt.scale = 1.0f;
             if (PTR) {
                 if (!a0) {
-                    mt.A = static_cast<const TI*>(a.Aarr[pe]);
-                    mt.B = static_cast<const TI*>(a.Barr[pe]);
+                    mt.A = in_space<1>(static_cast<const TI*>(a.Aarr[pe]));
+                    mt.B = in_space<1>(static_cast<const TI*>(a.Barr[pe]));
                 }
-                mt.C = a.Carr[pe];
+                mt.C = in_space<1>(a.Carr[pe]);
             } else {
                 if (!a0) {
-                    mt.A = static_cast<const TI*>(a.A) + pe * a.strideA;
-                    mt.B = static_cast<const TI*>(a.B) + pe * a.strideB;
+                    mt.A = in_space<1>(static_cast<const TI*>(a.A) + pe * a.strideA);
+                    mt.B = in_space<1>(static_cast<const TI*>(a.B) + pe * a.strideB);
                 }
-                mt.C = a.C + pe * a.strideC;
+                mt.C = in_space<1>(a.C + pe * a.strideC);
             }
             if (a.scaleA) mt.scale = a.scaleA[pe] * a.scaleB[pe];
         }
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
 
     if (!PIPE) {
         for (int64_t grp = q; grp < ngroups; grp += W) {
-            LaneMat<T, TI> mats[U];
+            LaneMat<T, TI, 1> mats[U];
             setup(grp, mats);
             tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
         }
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
     // software pipeline across groups: loads of group grp + W are in flight
     // while group grp is multiplied and stored
     if (q >= ngroups) return;
-    LaneMat<T, TI> cur[U], nxt[U];
+    LaneMat<T, TI, 1> cur[U], nxt[U];
     TileRegs<T, TI, D, U> rc, rn;
     setup(q, cur);
     tile_load<T, TI, D, U, ACONT, BCONT>(cur, L, a0, b0, rc);

@@ -186,9 +186,9 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
     SBG_RUN_SPANS(r)
     SBG_ISSUE()
 
-    const TI* lA = reinterpret_cast<const TI*>(lds);
-    const TI* lB = reinterpret_cast<const TI*>(lds + offB);
-    T* lC = reinterpret_cast<T*>(lds + offC);
+    const auto lA = in_space<3>(reinterpret_cast<const TI*>(lds));
+    const auto lB = in_space<3>(reinterpret_cast<const TI*>(lds + offB));
+    const auto lC = in_space<3>(reinterpret_cast<T*>(lds + offC));
 
     for (; r < nruns; r += W) {
         SBG_COMMIT()
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
         const int ntiles = (ccnt + P - 1) / P;
         for (int tile = 0; tile < ntiles; ++tile) {
             const int mi0 = tile * P + L.sel;
-            LaneMat<T, TI> mt[1];
+            LaneMat<T, TI, 3> mt[1];
             mt[0].valid = mi0 < ccnt;
             const int mi = mt[0].valid ? mi0 : ccnt - 1;   // lanes past the run read its last matrix
             mt[0].m = m;

@@ -112,13 +112,39 @@ __device__ __forceinline__ float round_bf16(float x) {
 }
 
 // Read CNT consecutive elements starting at p as one (element-aligned) access.
-template <typename X, int CNT>
-__device__ __forceinline__ void vload(X (&v)[CNT], const X* p) {
+template <typename X, int CNT, typename P>
+__device__ __forceinline__ void vload(X (&v)[CNT], P p) {
     __builtin_memcpy(v, p, sizeof(X) * CNT);
 }
-template <typename X, int CNT>
-__device__ __forceinline__ void vstore(X* p, const X (&v)[CNT]) {
+template <typename X, int CNT, typename P>
+__device__ __forceinline__ void vstore(P p, const X (&v)[CNT]) {
     __builtin_memcpy(p, v, sizeof(X) * CNT);
+}
+// One element through a pointer of any address space (vector structs have no
+// assignment from address-space-qualified objects).
+template <typename X, typename P>
+__device__ __forceinline__ X ld1(P p) {
+    X v;
+    __builtin_memcpy(&v, p, sizeof(X));
+    return v;
+}
+template <typename X, typename P>
+__device__ __forceinline__ void st1(P p, const X& v) {
+    __builtin_memcpy(p, &v, sizeof(X));
+}
+
+// Pointers in a named address space: 1 = global memory (the direct and
+// variable-size kernels), 3 = LDS (the staged kernel).  Matrix pointers that
+// the kernels read from memory (pointer arrays, var-size records) would
+// otherwise be generic, and generic accesses compile to flat instructions
+// (counted against both the vector-memory and the LDS counters).
+template <typename X, int AS> struct SpacePtr;
+template <typename X> struct SpacePtr<X, 1> { using type = __attribute__((address_space(1))) X*; };
+template <typename X> struct SpacePtr<X, 3> { using type = __attribute__((address_space(3))) X*; };
+template <int AS, typename X>
+__device__ __forceinline__ typename SpacePtr<X, AS>::type in_space(X* p)
+{
+    return (typename SpacePtr<X, AS>::type)p;
 }
 
 // Epilogue of one entry: alpha * acc + beta * c (real or complex), with the
@@ -155,11 +181,11 @@ __device__ __forceinline__ T axpby(typename Tr<T>::R ar, typename Tr<T>::R ai, t
 // One lane's view of the matrix it serves in a tile.  Output register r of
 // the lane holds C(i, j) with (i, j) = (orow[r], ij), or (ij, orow[r]) when
 // the MFMA operands are swapped.
-template <typename T, typename TI>
+template <typename T, typename TI, int AS = 1>
 struct LaneMat {
-    const TI* A;
-    const TI* B;
-    T* C;
+    typename SpacePtr<const TI, AS>::type A;
+    typename SpacePtr<const TI, AS>::type B;
+    typename SpacePtr<T, AS>::type C;
     int m, n, k;
     int64_t lda, ldb, ldc;
     float scale;   // sA * sB for scaled narrow inputs, 1 otherwise
@@ -214,15 +240,15 @@ struct TileRegs {
 // together.  The caller's pointers must be valid whenever the tile is live
 // (tiles past the batch carry a valid matrix's pointers with valid = false),
 // except A and B when alpha == 0 or k == 0 (then they are not read).
-template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT>
-__device__ __forceinline__ void tile_load(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT, int AS>
+__device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                           bool a0, bool b0, TileRegs<T, TI, D, U>& t)
 {
     using M = Mfma<typename Tr<T>::R>;
     constexpr int KB = D / 4;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const LaneMat<T, TI>& mt = mats[u];
+        const LaneMat<T, TI, AS>& mt = mats[u];
         const bool row_ok = L.ij < mt.m;
         const bool col_ok = L.ij < mt.n;
         // vector loads of the k-contiguous operands when k is a multiple of
@@ -230,50 +256,50 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI> (&mats)[U], const
         const bool kvec = (mt.k % KB) == 0;
         if (!a0 && mt.k > 0) {
             if (ACONT) {
-                const TI* src = mt.A + L.ij * mt.lda + L.kk0;
+                const auto src = mt.A + L.ij * mt.lda + L.kk0;
                 if (kvec) {
                     vload<TI, KB>(t.va[u], (row_ok && L.kk0 < mt.k) ? src : mt.A);
                 } else {
 #pragma unroll
                     for (int kb = 0; kb < KB; ++kb)
-                        t.va[u][kb] = *((row_ok && L.kk0 + kb < mt.k) ? src + kb : mt.A);
+                        t.va[u][kb] = ld1<TI>((row_ok && L.kk0 + kb < mt.k) ? src + kb : mt.A);
                 }
             } else {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb)
-                    t.va[u][kb] = *((row_ok && L.kk0 + kb < mt.k) ? mt.A + L.ij + (L.kk0 + kb) * mt.lda : mt.A);
+                    t.va[u][kb] = ld1<TI>((row_ok && L.kk0 + kb < mt.k) ? mt.A + L.ij + (L.kk0 + kb) * mt.lda : mt.A);
             }
             if (BCONT) {
-                const TI* src = mt.B + L.ij * mt.ldb + L.kk0;
+                const auto src = mt.B + L.ij * mt.ldb + L.kk0;
                 if (kvec) {
                     vload<TI, KB>(t.vb[u], (col_ok && L.kk0 < mt.k) ? src : mt.B);
                 } else {
 #pragma unroll
                     for (int kb = 0; kb < KB; ++kb)
-                        t.vb[u][kb] = *((col_ok && L.kk0 + kb < mt.k) ? src + kb : mt.B);
+                        t.vb[u][kb] = ld1<TI>((col_ok && L.kk0 + kb < mt.k) ? src + kb : mt.B);
                 }
             } else {
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb)
-                    t.vb[u][kb] = *((col_ok && L.kk0 + kb < mt.k) ? mt.B + L.ij + (L.kk0 + kb) * mt.ldb : mt.B);
+                    t.vb[u][kb] = ld1<TI>((col_ok && L.kk0 + kb < mt.k) ? mt.B + L.ij + (L.kk0 + kb) * mt.ldb : mt.B);
             }
         }
         if (!b0) {
             if (M::swap) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    t.cin[u][r] = *((row_ok && L.keep[r] && L.orow[r] < mt.n) ? mt.C + L.ij + L.orow[r] * mt.ldc
-                                                                                 : mt.C);
+                    t.cin[u][r] = ld1<T>((row_ok && L.keep[r] && L.orow[r] < mt.n) ? mt.C + L.ij + L.orow[r] * mt.ldc
+                                                                                    : mt.C);
             } else {
                 // rows 4g'..4g'+3 of the lane's column: a vector when m is a
                 // multiple of 4 (each lane's rows whole or past m)
-                const T* cb = mt.C + L.ij * mt.ldc;
+                const auto cb = mt.C + L.ij * mt.ldc;
                 if (M::rows_contig && (mt.m & 3) == 0) {
                     vload<T, 4>(t.cin[u], (col_ok && L.keep[0] && L.orow[0] < mt.m) ? cb + L.orow[0] : mt.C);
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        t.cin[u][r] = *((col_ok && L.keep[r] && L.orow[r] < mt.m) ? cb + L.orow[r] : mt.C);
+                        t.cin[u][r] = ld1<T>((col_ok && L.keep[r] && L.orow[r] < mt.m) ? cb + L.orow[r] : mt.C);
                 }
             }
         }
@@ -283,8 +309,8 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI> (&mats)[U], const
 // Decode, multiply (MFMA steps) and write back U tiles whose loads were
 // issued by tile_load.  MODE 0: plain; MODE 1: BF16x3 (each binary32 operand
 // split into bf16 hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
-template <typename T, typename TI, int MODE, int D, int U>
-__device__ __forceinline__ void tile_finish(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+template <typename T, typename TI, int MODE, int D, int U, int AS>
+__device__ __forceinline__ void tile_finish(const LaneMat<T, TI, AS> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                             const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
                                             float b_conj, const TileRegs<T, TI, D, U>& t)
 {
@@ -297,7 +323,7 @@ __device__ __forceinline__ void tile_finish(const LaneMat<T, TI> (&mats)[U], con
     const R br_ = re_of<T>(beta), bi_ = im_of<T>(beta);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const LaneMat<T, TI>& mt = mats[u];
+        const LaneMat<T, TI, AS>& mt = mats[u];
         const bool row_ok = L.ij < mt.m;
         const bool col_ok = L.ij < mt.n;
         const bool live = mt.valid && !a0;
@@ -356,23 +382,23 @@ __device__ __forceinline__ void tile_finish(const LaneMat<T, TI> (&mats)[U], con
         if (M::swap) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (L.keep[r] && L.orow[r] < mt.n) mt.C[L.ij + L.orow[r] * mt.ldc] = out[r];
+                if (L.keep[r] && L.orow[r] < mt.n) st1<T>(mt.C + L.ij + L.orow[r] * mt.ldc, out[r]);
         } else {
-            T* cb = mt.C + L.ij * mt.ldc;
+            const auto cb = mt.C + L.ij * mt.ldc;
             if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
                 vstore<T, 4>(cb + L.orow[0], out);
             } else {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (L.keep[r] && L.orow[r] < mt.m) cb[L.orow[r]] = out[r];
+                    if (L.keep[r] && L.orow[r] < mt.m) st1<T>(cb + L.orow[r], out[r]);
             }
         }
     }
 }
 
 // U tiles of one wavefront: all loads first, then the MFMA steps and epilogues.
-template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT>
-__device__ __forceinline__ void tile_group(const LaneMat<T, TI> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
+template <typename T, typename TI, int MODE, int D, int U, bool ACONT, bool BCONT, int AS>
+__device__ __forceinline__ void tile_group(const LaneMat<T, TI, AS> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                            const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
                                            float b_conj)
 {

@@ -70,11 +70,11 @@ __device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, in
     constexpr int P = 16 / D;
     constexpr int U = Unroll<T, D>::value;
     const LaneGeom<D, R> L;
-    LaneMat<T, TI> mats[U];
+    LaneMat<T, TI, 1> mats[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t li = (grp * U + u) * P + L.sel;
-        LaneMat<T, TI>& mt = mats[u];
+        LaneMat<T, TI, 1>& mt = mats[u];
         mt.valid = li < count;
         // lanes past the list carry its last matrix (loads in bounds, nothing stored)
         const VbRec r = list[mt.valid ? li : count - 1];
@@ -87,10 +87,10 @@ __device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, in
         mt.A = nullptr;
         mt.B = nullptr;
         if (!a0) {
-            mt.A = static_cast<const TI*>(r.A);
-            mt.B = static_cast<const TI*>(r.B);
+            mt.A = in_space<1>(static_cast<const TI*>(r.A));
+            mt.B = in_space<1>(static_cast<const TI*>(r.B));
         }
-        mt.C = static_cast<T*>(r.C);
+        mt.C = in_space<1>(static_cast<T*>(r.C));
         mt.scale = r.scale;
     }
     tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
