@@ -189,7 +189,8 @@ def main():
     if not args.no_extras:
         secondary = {}
         for name, fn in (("small_batch", sec_small_batch), ("complex", sec_complex_sweep),
-                         ("varsize_precision", sec_varsize_modes), ("fem", sec_fem_chain)):
+                         ("varsize_precision", sec_varsize_modes), ("fem", sec_fem_chain),
+                         ("fixed_operand", sec_fixed_operand), ("batch_sweep", sec_batch_sweep)):
             try:
                 secondary[name] = fn(stream)
             except Exception as e:  # a secondary failure must not hide the primary line
@@ -477,6 +478,84 @@ def sec_fem_chain(stream):
                         "hbm_frac": round(fby / tf / HBM_PEAK, 4)},
             "backward": {"us": round(tb * 1e6, 1), "gflops": round(bfl / tb / 1e9, 1),
                          "hbm_frac": round(bby / tb / HBM_PEAK, 4)}}
+
+
+def _time_calls(call, reps, flush):
+    """Median seconds of `call` (eager launches on the current stream), the
+    Infinity Cache flushed before each one outside the timed interval."""
+    import torch
+    ts = []
+    cur = torch.cuda.current_stream()
+    call()
+    for _ in range(reps):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        call()
+        e1.record(cur)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def sec_fixed_operand(stream):
+    """The fixed-operand case the paper names as a next step (Sec. 9): one A
+    (strideA = 0) or one B (strideB = 0) shared by the whole batch, against
+    the ordinary batch; N = 100,000, NN, alpha = 1.5, beta = -0.5.  The HBM
+    fraction counts the shared matrix once."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    N = 100_000
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 6)
+    out = {}
+    for tname, tdt, esz in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        for n in (8, 16):
+            el = N * n * n
+            A = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            B = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            C = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            res = {}
+            for case, sa, sb in (("batched", n * n, n * n), ("shared_A", 0, n * n), ("shared_B", n * n, 0)):
+                call = lambda: sbg.gemm_strided("N", "N", n, n, n, 1.5, A, n, sa, B, n, sb, -0.5, C, n,  # noqa: E731
+                                                n * n, N)
+                t = _time_calls(call, 7, flush)
+                byts = esz * n * n * (N * (2 + (sa > 0) + (sb > 0)) + (sa == 0) + (sb == 0))
+                res[case] = {"us": round(t * 1e6, 1), "gflops": round(2.0 * n ** 3 * N / t / 1e9, 1),
+                             "hbm_frac": round(byts / t / HBM_PEAK, 4)}
+            out[f"{tname}_n{n}"] = res
+            del A, B, C
+    return out
+
+
+def sec_batch_sweep(stream):
+    """Batch-size sweep (the paper's plateau question, Sec. 8): fp32 NN,
+    alpha = 1.5, beta = -0.5, n in {8, 16}, N from 2,000 to 1,000,000."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 7)
+    out = {}
+    for n in (8, 16):
+        row = {}
+        for N in (2000, 5000, 20000, 100_000, 1_000_000):
+            el = N * n * n
+            A = torch.rand(el, generator=gen, device="cuda") * 2 - 1
+            B = torch.rand(el, generator=gen, device="cuda") * 2 - 1
+            C = torch.rand(el, generator=gen, device="cuda") * 2 - 1
+            call = lambda: sbg.gemm_strided("N", "N", n, n, n, 1.5, A, n, n * n, B, n, n * n, -0.5, C, n,  # noqa: E731
+                                            n * n, N)
+            t = _time_calls(call, 7, flush)
+            row[str(N)] = {"us": round(t * 1e6, 2), "gflops": round(2.0 * n ** 3 * N / t / 1e9, 1),
+                           "hbm_frac": round(16.0 * n * n * N / t / HBM_PEAK, 4)}
+            del A, B, C
+        out[f"f32_n{n}"] = row
+    return out
 
 
 def cpu_baseline(calls, sample):

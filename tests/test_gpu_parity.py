@@ -214,3 +214,22 @@ def test_full_size_complex(gpu_lib, dtype):
                 c.ta, c.tb = ta, tb
                 say(f"full-size {np.dtype(dtype).name} {ta}{tb} n={s} N={N}")
                 check(c, c.run_gpu(), idx=idx, label="fullsize-c")
+
+
+@pytest.mark.parametrize("dtype", REAL, ids=lambda d: np.dtype(d).name)
+def test_full_size_fixed_operand(gpu_lib, dtype):
+    """The fixed-operand case (Sec. 9 outlook): one A (strideA = 0) or one B
+    (strideB = 0) for the whole N = 100,000 batch, sampled against the
+    oracle, n in {8, 13, 16} (direct and staged sizes)."""
+    N = 100_000
+    g = inputs.rng(209)
+    for s in (8, 13, 16):
+        for shared in ("A", "B"):
+            c = Case(dtype, "N", "N", s, s, s, N, 1.5, -0.5, g)
+            if shared == "A":
+                c.sA = 0
+            else:
+                c.sB = 0
+            idx = _sample(N, g, 300)
+            say(f"fixed operand {np.dtype(dtype).name} n={s} shared {shared}")
+            check(c, c.run_gpu(), idx=idx, label="fixed")
