@@ -103,6 +103,12 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const GemmArgs<T> a)
                 mt.C = in_space<1>(a.C + pe * a.strideC);
             }
             if (a.scaleA) mt.scale = a.scaleA[pe] * a.scaleB[pe];
+            // over-reads of up to 3 elements stay inside the buffer when
+            // later matrices of the batch follow at least that far on
+            const int64_t after = a.batch - 1 - pe;
+            mt.overA = !PTR && after * a.strideA >= 3;
+            mt.overB = !PTR && after * a.strideB >= 3;
+            mt.overC = !PTR && after * a.strideC >= 3;
         }
     };
 

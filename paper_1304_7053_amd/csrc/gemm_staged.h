@@ -218,6 +218,7 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
             mt[0].B = lB + mi * eB;
             mt[0].C = lC + mi * eC;
             mt[0].scale = 1.0f;   // per-matrix scales never take this kernel
+            mt[0].overA = mt[0].overB = mt[0].overC = false;
             tile_group<T, TI, MODE, D, 1, ACONT, BCONT>(mt, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
         }
         wave_lds_sync();

@@ -190,6 +190,11 @@ struct LaneMat {
     int64_t lda, ldb, ldc;
     float scale;   // sA * sB for scaled narrow inputs, 1 otherwise
     bool valid;
+    // A vector of the k-contiguous operand (or of C's rows) may run up to 3
+    // elements past the end of this matrix's row: set only when those
+    // elements lie inside the caller's buffer (a later matrix of the same
+    // strided batch); the extra elements are masked, never used or stored.
+    bool overA, overB, overC;
 };
 
 // Per-lane constants of the packed tile layout.
@@ -257,7 +262,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
         if (!a0 && mt.k > 0) {
             if (ACONT) {
                 const auto src = mt.A + L.ij * mt.lda + L.kk0;
-                if (kvec) {
+                if (kvec || mt.overA) {
                     vload<TI, KB>(t.va[u], (row_ok && L.kk0 < mt.k) ? src : mt.A);
                 } else {
 #pragma unroll
@@ -271,7 +276,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
             }
             if (BCONT) {
                 const auto src = mt.B + L.ij * mt.ldb + L.kk0;
-                if (kvec) {
+                if (kvec || mt.overB) {
                     vload<TI, KB>(t.vb[u], (col_ok && L.kk0 < mt.k) ? src : mt.B);
                 } else {
 #pragma unroll
@@ -294,7 +299,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
                 // rows 4g'..4g'+3 of the lane's column: a vector when m is a
                 // multiple of 4 (each lane's rows whole or past m)
                 const auto cb = mt.C + L.ij * mt.ldc;
-                if (M::rows_contig && (mt.m & 3) == 0) {
+                if (M::rows_contig && ((mt.m & 3) == 0 || mt.overC)) {
                     vload<T, 4>(t.cin[u], (col_ok && L.keep[0] && L.orow[0] < mt.m) ? cb + L.orow[0] : mt.C);
                 } else {
 #pragma unroll

@@ -92,6 +92,7 @@ __device__ __forceinline__ void vb_process(const GemmArgs<T>& a, int64_t grp, in
         }
         mt.C = in_space<1>(static_cast<T*>(r.C));
         mt.scale = r.scale;
+        mt.overA = mt.overB = mt.overC = false;   // each matrix may be its own allocation
     }
     tile_group<T, TI, MODE, D, U, ACONT, BCONT>(mats, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
 }
