@@ -258,6 +258,15 @@ __host__ __device__ inline int size_class(int m, int n, int k)
     return mx <= 4 ? 4 : (mx <= 8 ? 8 : 16);
 }
 
+// Do runs of G packed matrices span whole 16-byte chunks of every operand
+// (A and B at ei bytes per element, C at ec)?  Then the LDS-staged kernel
+// needs no span tails for full runs.
+inline bool staged_whole_chunks(int m, int n, int k, int G, int ei, int ec)
+{
+    const int64_t g = G;
+    return (g * m * k * ei) % 16 == 0 && (g * k * n * ei) % 16 == 0 && (g * m * n * ec) % 16 == 0;
+}
+
 // Packed layout: minimal leading dimensions and strides (lda, ldb are the
 // stored row counts, which depend on the ops).
 template <typename T>
@@ -342,9 +351,11 @@ int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
 {
     const auto tf = [](bool b) { return b ? "true" : "false"; };
     const int D = size_class(a.m, a.n, a.k);
-    if (staged_choice<T, T>(a, pointer_form) > 0)
-        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %s, 0, %d, %s, %s>(sbg::GemmArgs<%s>)",
-                        TypeName<T>::s, TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans), TypeName<T>::s);
+    const int G = staged_choice<T, T>(a, pointer_form);
+    if (G > 0)
+        return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %s, 0, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans),
+                        tf(staged_whole_chunks(a.m, a.n, a.k, G, (int)sizeof(T), (int)sizeof(T))), TypeName<T>::s);
     const int U = D == 4 ? choose_unroll<T, T, 4>(a) : (D == 8 ? choose_unroll<T, T, 8>(a) : choose_unroll<T, T, 16>(a));
     return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s, %s>(sbg::GemmArgs<%s>)",
                     TypeName<T>::s, TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form),

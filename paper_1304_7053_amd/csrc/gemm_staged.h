@@ -40,7 +40,7 @@ __device__ __forceinline__ void wave_lds_sync()
 
 __host__ __device__ inline int align16i(int x) { return (x + 15) & ~15; }
 
-template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
+template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT, bool FAST>
 __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
 {
     using R = typename Tr<T>::R;
@@ -183,67 +183,171 @@ __global__ __launch_bounds__(256) void gemm_staged_kernel(const GemmArgs<T> a)
 
     u32x4 buf[MAXCH];
     u32x4 tbuf = {0u, 0u, 0u, 0u};
-    SBG_RUN_SPANS(r)
-    SBG_ISSUE()
 
     const auto lA = in_space<3>(reinterpret_cast<const TI*>(lds));
     const auto lB = in_space<3>(reinterpret_cast<const TI*>(lds + offB));
     const auto lC = in_space<3>(reinterpret_cast<T*>(lds + offC));
 
-    for (; r < nruns; r += W) {
-        SBG_COMMIT()
-        wave_lds_sync();
-        const int ccnt = cnt, cSC = SC;
-        unsigned char* cgC = gC;
-        // next run's chunks: in flight while this run computes
-        if (r + W < nruns) {
-            SBG_RUN_SPANS(r + W)
-            SBG_ISSUE()
+    // tiles of a run of CCNT matrices from LDS: each lane's matrix mi, operand
+    // entries gathered with the op folded into the LDS addressing
+#define SBG_COMPUTE(CCNT)                                                           \
+    {                                                                               \
+        const int ccnt_ = (CCNT);                                                   \
+        const int ntiles = (ccnt_ + P - 1) / P;                                     \
+        for (int tile = 0; tile < ntiles; ++tile) {                                 \
+            const int mi0 = tile * P + L.sel;                                       \
+            LaneMat<T, TI, 3> mt[1];                                                \
+            mt[0].valid = mi0 < ccnt_;                                              \
+            /* lanes past the run read its last matrix */                          \
+            const int mi = mt[0].valid ? mi0 : ccnt_ - 1;                           \
+            mt[0].m = m;                                                            \
+            mt[0].n = n;                                                            \
+            mt[0].k = k;                                                            \
+            mt[0].lda = ACONT ? k : m;                                              \
+            mt[0].ldb = BCONT ? k : n;                                              \
+            mt[0].ldc = m;                                                          \
+            mt[0].A = lA + mi * eA;                                                 \
+            mt[0].B = lB + mi * eB;                                                 \
+            mt[0].C = lC + mi * eC;                                                 \
+            mt[0].scale = 1.0f; /* per-matrix scales never take this kernel */      \
+            mt[0].overA = mt[0].overB = mt[0].overC = false;                        \
+            tile_group<T, TI, MODE, D, 1, ACONT, BCONT>(mt, L, alpha, beta, a0, b0, \
+                                                        a.a_conj, a.b_conj);        \
+        }                                                                           \
+    }
+    // C span LDS -> HBM for a run of the general path: whole chunks, then the
+    // overlapping tail
+#define SBG_STORE(CGC, CSC)                                                         \
+    {                                                                               \
+        const int FC = (CSC) >> 4;                                                  \
+        const int nt = (FC + 63) >> 6;                                              \
+        _Pragma("unroll") for (int t = 0; t < MAXCH; ++t) {                         \
+            if (t < nt) {                                                           \
+                const int q = lane + 64 * t;                                        \
+                if (q < FC) {                                                       \
+                    const u32x4 v = *reinterpret_cast<const u32x4*>(lds + offC + 16 * q); \
+                    *reinterpret_cast<u32x4a4*>((CGC) + 16 * q) = v;                \
+                }                                                                   \
+            }                                                                       \
+        }                                                                           \
+        if (lane == 0 && ((CSC) & 15)) {                                            \
+            const unsigned int* w = reinterpret_cast<const unsigned int*>(lds + offC + (CSC) - 16); \
+            const u32x4 v = {w[0], w[1], w[2], w[3]};                               \
+            *reinterpret_cast<u32x4a4*>((CGC) + (CSC) - 16) = v;                    \
+        }                                                                           \
+    }
+
+    // Fast-path load and LDS write of one full run through the slot table
+#define SBG_FAST_ISSUE(RR)                                                          \
+    {                                                                               \
+        const int64_t p0_ = (RR) * G;                                               \
+        const unsigned char* bA_ = gA0 + p0_ * eA * EI;                             \
+        const unsigned char* bB_ = gB0 + p0_ * eB * EI;                             \
+        const unsigned char* bC_ = gC0 + p0_ * eC * EC;                             \
+        _Pragma("unroll") for (int t = 0; t < MAXCH; ++t) {                         \
+            const unsigned w_ = slot[t];                                            \
+            const unsigned j_ = w_ >> 28;                                           \
+            const unsigned char* b_ = j_ == 0 ? bA_ : (j_ == 1 ? bB_ : bC_);        \
+            buf[t] = *reinterpret_cast<const u32x4a4*>(b_ + (w_ & 0x3FFF));         \
+        }                                                                           \
+    }
+#define SBG_FAST_COMMIT(NT)                                                         \
+    {                                                                               \
+        _Pragma("unroll") for (int t = 0; t < MAXCH; ++t) {                         \
+            if (t < (NT))                                                           \
+                *reinterpret_cast<u32x4*>(lds + ((slot[t] >> 14) & 0x3FFF)) = buf[t]; \
+        }                                                                           \
+    }
+
+    if constexpr (FAST) {
+        // Full runs (G matrices) whose spans are whole 16-byte chunks (the
+        // host prefers such G and picks this instance only then): every full
+        // run has the same chunk list, so each lane packs, per slot, the
+        // chunk's byte offset in its span (14 bits), its LDS offset (14 bits)
+        // and its span (2 bits) once; a run then only selects the span's
+        // base.  Loads are unconditional (a conditional load would leave the
+        // buffer registers to be merged across paths); only slots of the list
+        // are written to LDS.  The last, shorter run takes the general code.
+        const int fSA = a0 ? 0 : G * eA * EI, fSB = a0 ? 0 : G * eB * EI;
+        const int fSC = G * eC * EC, fSCin = b0 ? 0 : fSC;
+        const int64_t nfull = a.batch / G;
+        const int fFA = fSA >> 4, fFB = fSB >> 4, fFT = fFA + fFB + (fSCin >> 4);
+        const int fNT = (fFT + 63) >> 6;            // load slots of a full run
+        const int fFC = fSC >> 4;
+        const int fNC = (fFC + 63) >> 6;            // store slots of a full run
+        unsigned int slot[MAXCH];
+#pragma unroll
+        for (int t = 0; t < MAXCH; ++t) {
+            // every slot loads on every full run: past the list it repeats the
+            // last chunk; with nothing to load (alpha = beta = 0) it reads the
+            // head of the run's C span, which a full run always has, unused
+            int q = lane + 64 * t;
+            q = q < fFT ? q : (fFT > 0 ? fFT - 1 : 0);
+            const int j = q < fFA ? 0 : (q < fFA + fFB ? 1 : 2);
+            const int off = 16 * (j == 0 ? q : (j == 1 ? q - fFA : q - fFA - fFB));
+            const int dst = (j == 0 ? 0 : (j == 1 ? offB : offC)) + off;
+            slot[t] = (unsigned)off | ((unsigned)dst << 14) | ((unsigned)j << 28);
         }
-        // tiles of the run from LDS: each lane's matrix mi, operand entries
-        // gathered with the op folded into the LDS addressing
-        const int ntiles = (ccnt + P - 1) / P;
-        for (int tile = 0; tile < ntiles; ++tile) {
-            const int mi0 = tile * P + L.sel;
-            LaneMat<T, TI, 3> mt[1];
-            mt[0].valid = mi0 < ccnt;
-            const int mi = mt[0].valid ? mi0 : ccnt - 1;   // lanes past the run read its last matrix
-            mt[0].m = m;
-            mt[0].n = n;
-            mt[0].k = k;
-            mt[0].lda = ACONT ? k : m;
-            mt[0].ldb = BCONT ? k : n;
-            mt[0].ldc = m;
-            mt[0].A = lA + mi * eA;
-            mt[0].B = lB + mi * eB;
-            mt[0].C = lC + mi * eC;
-            mt[0].scale = 1.0f;   // per-matrix scales never take this kernel
-            mt[0].overA = mt[0].overB = mt[0].overC = false;
-            tile_group<T, TI, MODE, D, 1, ACONT, BCONT>(mt, L, alpha, beta, a0, b0, a.a_conj, a.b_conj);
-        }
-        wave_lds_sync();
-        // C span LDS -> HBM: whole chunks, then the overlapping tail
-        {
-            const int FC = cSC >> 4;
-            const int nt = (FC + 63) >> 6;
+        // Full runs through the slot table, the next run's loads in flight
+        // while this one computes.  One loop with one load path, so the wait
+        // before each LDS write counts only the loads still ahead of it.
+        if (r < nfull) SBG_FAST_ISSUE(r)
+        for (; r < nfull; r += W) {
+            // slot counts re-read each run: kept as two scalars instead of
+            // sixteen hoisted lane masks
+            int nt = fNT, nc = fNC;
+            __asm__ volatile("" : "+s"(nt), "+s"(nc));
+            SBG_FAST_COMMIT(nt)
+            wave_lds_sync();
+            if (r + W < nfull) SBG_FAST_ISSUE(r + W)
+            SBG_COMPUTE(G)
+            wave_lds_sync();
+            unsigned char* cgC = gC0 + r * G * eC * EC;
 #pragma unroll
             for (int t = 0; t < MAXCH; ++t) {
-                if (t < nt) {
-                    const int q = lane + 64 * t;
-                    if (q < FC) {
-                        const u32x4 v = *reinterpret_cast<const u32x4*>(lds + offC + 16 * q);
-                        *reinterpret_cast<u32x4a4*>(cgC + 16 * q) = v;
-                    }
+                if (t < nc) {
+                    int q = lane + 64 * t;
+                    q = q < fFC ? q : fFC - 1;   // repeats: the same bytes to the same address
+                    const u32x4 v = *reinterpret_cast<const u32x4*>(lds + offC + 16 * q);
+                    *reinterpret_cast<u32x4a4*>(cgC + 16 * q) = v;
                 }
             }
-            if (lane == 0 && (cSC & 15)) {
-                const unsigned int* w = reinterpret_cast<const unsigned int*>(lds + offC + cSC - 16);
-                const u32x4 v = {w[0], w[1], w[2], w[3]};
-                *reinterpret_cast<u32x4a4*>(cgC + cSC - 16) = v;
-            }
+            wave_lds_sync();
         }
-        wave_lds_sync();
+        // the last, shorter run (index nfull) falls to at most one wave
+        if (r < nruns) {
+            SBG_RUN_SPANS(r)
+            SBG_ISSUE()
+            SBG_COMMIT()
+            wave_lds_sync();
+            SBG_COMPUTE(cnt)
+            wave_lds_sync();
+            SBG_STORE(gC, SC)
+        }
+    } else {
+        // General path: runs with tails, the next run's chunks in flight
+        // while this run computes.
+        SBG_RUN_SPANS(r)
+        SBG_ISSUE()
+        for (; r < nruns; r += W) {
+            SBG_COMMIT()
+            wave_lds_sync();
+            const int ccnt = cnt, cSC = SC;
+            unsigned char* cgC = gC;
+            if (r + W < nruns) {
+                SBG_RUN_SPANS(r + W)
+                SBG_ISSUE()
+            }
+            SBG_COMPUTE(ccnt)
+            wave_lds_sync();
+            SBG_STORE(cgC, cSC)
+            wave_lds_sync();
+        }
     }
+#undef SBG_COMPUTE
+#undef SBG_STORE
+#undef SBG_FAST_ISSUE
+#undef SBG_FAST_COMMIT
 #undef SBG_ISSUE
 #undef SBG_COMMIT
 #undef SBG_TAIL
@@ -267,10 +371,18 @@ inline int staged_run_length(int m, int n, int k, int64_t batch, int min_waves)
     // enough runs to keep min_waves waves busy
     const int64_t fair = (batch + min_waves - 1) / min_waves;
     if (fair < G) G = fair < 1 ? 1 : fair;
-    // whole tiles per run, and whole 4-byte words for narrow inputs
+    // whole tiles per run, and whole 4-byte words for narrow inputs; when a
+    // run of whole 16-byte chunks fits (a multiple of `unit` matrices), take
+    // the largest such G: full runs then need no tails (the fast path)
     const int64_t P = 16 / size_class(m, n, k);
     const int64_t step = (ei < 4 && P < 4) ? 4 : P;
-    if (G >= step) G -= G % step;
+    const auto whole16 = [](int64_t b) { const int64_t low = b & -b; return 16 / (low < 16 ? low : 16); };
+    int64_t unit = step;
+    for (const int64_t b : {(int64_t)m * k * ei, (int64_t)k * n * ei, (int64_t)m * n * ec})
+        unit = whole16(b) > unit ? whole16(b) : unit;
+    if (G >= unit) G -= G % unit;
+    else if (unit * per <= room) G = unit;
+    else if (G >= step) G -= G % step;
     else if (step * per <= room) G = step;
     if (G > batch) G = batch;
     const int64_t last = batch - ((batch - 1) / G) * G;   // matrices in the last run
@@ -284,7 +396,10 @@ inline int staged_run_length(int m, int n, int k, int64_t batch, int min_waves)
 template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream)
 {
-    auto kern = gemm_staged_kernel<T, TI, MODE, D, ACONT, BCONT>;
+    // the slot-table kernel only where every full run is whole 16-byte chunks
+    const bool fast = staged_whole_chunks(a.m, a.n, a.k, a.G, (int)sizeof(TI), (int)sizeof(T));
+    auto kern = fast ? gemm_staged_kernel<T, TI, MODE, D, ACONT, BCONT, true>
+                     : gemm_staged_kernel<T, TI, MODE, D, ACONT, BCONT, false>;
     const int64_t runs = (a.batch + a.G - 1) / a.G;
     const int64_t grid = persistent_grid(kern, runs, a);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);

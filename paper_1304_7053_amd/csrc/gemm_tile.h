@@ -257,12 +257,17 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
         const bool row_ok = L.ij < mt.m;
         const bool col_ok = L.ij < mt.n;
         // vector loads of the k-contiguous operands when k is a multiple of
-        // the lane's k-run (each run then whole or past k), scalars otherwise
+        // the lane's k-run (each run then whole or past k) or the run may be
+        // over-read, scalars otherwise; decided by a wave vote, so the choice
+        // is uniform even when the lanes serve matrices of different sizes
         const bool kvec = (mt.k % KB) == 0;
+        const bool vecA = __all(kvec || mt.overA);
+        const bool vecB = __all(kvec || mt.overB);
+        const bool vecC = __all((mt.m & 3) == 0 || mt.overC);
         if (!a0 && mt.k > 0) {
             if (ACONT) {
                 const auto src = mt.A + L.ij * mt.lda + L.kk0;
-                if (kvec || mt.overA) {
+                if (vecA) {
                     vload<TI, KB>(t.va[u], (row_ok && L.kk0 < mt.k) ? src : mt.A);
                 } else {
 #pragma unroll
@@ -276,7 +281,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
             }
             if (BCONT) {
                 const auto src = mt.B + L.ij * mt.ldb + L.kk0;
-                if (kvec || mt.overB) {
+                if (vecB) {
                     vload<TI, KB>(t.vb[u], (col_ok && L.kk0 < mt.k) ? src : mt.B);
                 } else {
 #pragma unroll
@@ -299,7 +304,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
                 // rows 4g'..4g'+3 of the lane's column: a vector when m is a
                 // multiple of 4 (each lane's rows whole or past m)
                 const auto cb = mt.C + L.ij * mt.ldc;
-                if (M::rows_contig && ((mt.m & 3) == 0 || mt.overC)) {
+                if (M::rows_contig && vecC) {
                     vload<T, 4>(t.cin[u], (col_ok && L.keep[0] && L.orow[0] < mt.m) ? cb + L.orow[0] : mt.C);
                 } else {
 #pragma unroll
