@@ -190,7 +190,8 @@ def main():
         secondary = {}
         for name, fn in (("small_batch", sec_small_batch), ("complex", sec_complex_sweep),
                          ("varsize_precision", sec_varsize_modes), ("fem", sec_fem_chain),
-                         ("fixed_operand", sec_fixed_operand), ("batch_sweep", sec_batch_sweep)):
+                         ("fixed_operand", sec_fixed_operand), ("batch_sweep", sec_batch_sweep),
+                         ("large_sizes", sec_large_sizes)):
             try:
                 secondary[name] = fn(stream)
             except Exception as e:  # a secondary failure must not hide the primary line
@@ -555,6 +556,37 @@ def sec_batch_sweep(stream):
                            "hbm_frac": round(16.0 * n * n * N / t / HBM_PEAK, 4)}
             del A, B, C
         out[f"f32_n{n}"] = row
+    return out
+
+
+def sec_large_sizes(stream):
+    """Sizes above 16 (the sub-blocked kernel, the paper's extension remark):
+    square n in {24, 32, 48, 64}, NN and TN, alpha = 1.5, beta = -0.5, with
+    about 400 MB per fp32 operand (800 MB fp64).  HBM fraction counts A, B
+    and C read once and C written once (the kernel re-reads A and B blocks
+    from L2 for each block of C)."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 8)
+    out = {}
+    for tname, tdt, esz in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        for n in (24, 32, 48, 64):
+            N = 100_000_000 // (n * n)
+            el = N * n * n
+            A = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            B = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            C = torch.rand(el, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            for ops in ("NN", "TN"):
+                call = lambda: sbg.gemm_strided(ops[0], ops[1], n, n, n, 1.5, A, n, n * n, B, n, n * n,  # noqa: E731
+                                                -0.5, C, n, n * n, N)
+                t = _time_calls(call, 5, flush)
+                out[f"{tname}_n{n}_{ops}"] = {"N": N, "us": round(t * 1e6, 1),
+                                               "gflops": round(2.0 * n ** 3 * N / t / 1e9, 1),
+                                               "hbm_frac": round(4.0 * esz * el / t / HBM_PEAK, 4)}
+            del A, B, C
     return out
 
 

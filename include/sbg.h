@@ -6,7 +6,11 @@
  *
  *     C_p <- alpha * op(A_p) * op(B_p) + beta * C_p,      p = 0 .. batch_count-1,
  *
- * with C_p m x n, op(A_p) m x k, op(B_p) k x n, and 0 <= m, n, k <= 16.
+ * with C_p m x n, op(A_p) m x k, op(B_p) k x n.  The paper's kernels cover
+ * 0 <= m, n, k <= 16; the plain S/D/C/Z forms here also take larger sizes
+ * (cut into 16 x 16 output blocks and 16-wide k-chunks: the extension the
+ * paper says its method allows, Sec. 1, by sub-block products, Sec. 7), while
+ * the mixed-precision and variable-size forms keep the limit of 16.
  * op(X) is selected per operand by a character (Sec. 2; Sec. 5 argument list):
  *     'N'/'n'  X            'T'/'t'  X^T            'C'/'c'  X^H (conjugate transpose)
  *     'R'/'r'  conj(X), no transpose -- an extension not in the paper, used to
@@ -32,7 +36,8 @@
  *
  * Errors: SBG_INVALID_VALUE with the 1-based position of the first rejected
  * argument recorded for sbg_last_invalid_arg() (checked in argument order, as
- * BLAS's xerbla does); SBG_NOT_SUPPORTED for m, n or k above 16;
+ * BLAS's xerbla does); SBG_NOT_SUPPORTED for m, n or k above 16 in the
+ * mixed-precision, variable-size and quantiser entry points;
  * SBG_HIP_ERROR when the kernel launch fails.  Nothing is launched unless the
  * result is SBG_OK.
  *
@@ -82,7 +87,7 @@ typedef enum { SBG_MODE_PLAIN = 0, SBG_MODE_BF16X3 = 1 } sbg_compute_mode_t;
 /* ---- strided form: the paper's TGEMM_multi_uniform (Sec. 5) --------------
  * Arguments, in order (positions used by sbg_last_invalid_arg):
  *   1 transa, 2 transb   op characters (see above)
- *   3 m, 4 n, 5 k        sizes, 0..16
+ *   3 m, 4 n, 5 k        sizes, >= 0 (above 16: the sub-blocked kernel)
  *   6 alpha              pointer to the scalar (host or device, see mode)
  *   7 A                  device pointer to the (0,0) element of A_0
  *   8 lda                >= max(1, m) for op N/R, >= max(1, k) for T/C

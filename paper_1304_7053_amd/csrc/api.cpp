@@ -151,7 +151,8 @@ sbg_status_t prepare(char transa, char transb, int m, int n, int k,
                      const void* B, int ldb, const typename Scal<T>::api_t* beta,
                      const void* C, int ldc, int64_t batch, const Pos& pos,
                      GemmArgs<T>& args, bool& launch,
-                     const int64_t* strides /* strideA, strideB, strideC or null */)
+                     const int64_t* strides /* strideA, strideB, strideC or null */,
+                     bool any_size /* sizes above 16 (the sub-blocked kernel) accepted */)
 {
     launch = false;
     tl_last_invalid = 0;
@@ -181,7 +182,7 @@ sbg_status_t prepare(char transa, char transb, int m, int n, int k,
     if (strides && (strides[2] < 0 || (batch > 1 && strides[2] < (int64_t)ldc * n)))
         return reject(pos.ldc + 1);
     if (batch < 0) return reject(pos.batch);
-    if (m > 16 || n > 16 || k > 16) return SBG_NOT_SUPPORTED;
+    if (!any_size && (m > 16 || n > 16 || k > 16)) return SBG_NOT_SUPPORTED;
 
     if (!nonempty) return SBG_OK;
     if (host) {
@@ -243,7 +244,7 @@ sbg_status_t strided(char ta, char tb, int m, int n, int k, const typename Scal<
     static const Pos pos = {6, 7, 8, 10, 11, 13, 14, 15, 17};
     bool launch = false;
     const sbg_status_t st = prepare<T>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, batch, pos, a,
-                                       launch, strides);
+                                       launch, strides, true);
     if (st != SBG_OK || !launch) return st;
     return launch_plain<T>(a, false, stream);
 }
@@ -261,7 +262,7 @@ sbg_status_t pointers(char ta, char tb, int m, int n, int k, const typename Scal
     static const Pos pos = {6, 7, 8, 9, 10, 11, 12, 13, 14};
     bool launch = false;
     const sbg_status_t st = prepare<T>(ta, tb, m, n, k, alpha, Aarr, lda, Barr, ldb, beta, Carr, ldc, batch, pos,
-                                       a, launch, nullptr);
+                                       a, launch, nullptr, true);
     if (st != SBG_OK || !launch) return st;
     return launch_plain<T>(a, true, stream);
 }
@@ -473,7 +474,7 @@ sbg_status_t sbg_gemm_strided_batched_ex(char transa, char transb, int m, int n,
     static const sbg::Pos pos = {6, 7, 8, 11, 12, 15, 16, 17, 19};
     bool launch = false;
     const sbg_status_t st = sbg::prepare<float>(transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                                                batch_count, pos, a, launch, strides);
+                                                batch_count, pos, a, launch, strides, false);
     if (st != SBG_OK) return st;
     if ((scaleA == nullptr) != (scaleB == nullptr)) return sbg::reject(scaleA ? 14 : 10);
     if (ab_type == SBG_R_8F_E4M3 && !scaleA) return sbg::reject(10);

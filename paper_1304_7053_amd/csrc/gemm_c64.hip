@@ -1,5 +1,6 @@
 // Kernel instances for element type float2 (all size classes, both batch forms).
 #include "gemm_vbatched.h"
 #include "gemm_staged.h"
+#include "gemm_blocked.h"
 
 SBG_INSTANTIATE_GEMM(float2)

@@ -2,7 +2,8 @@
 // pointer-array forms.
 //
 // Computes C_p <- alpha op(A_p) op(B_p) + beta C_p (Sec. 2, Eq. (1)) for
-// m, n, k <= 16.  Design (what differs from the paper's Sec. 7 thread-per-
+// m, n, k <= 16 (larger sizes: gemm_blocked.h, whose blocks reuse the tile
+// routines here).  Design (what differs from the paper's Sec. 7 thread-per-
 // entry and register-blocked shared-memory kernels):
 //
 //  * One wavefront owns a "tile": 16/D independent matrices of size class D
@@ -42,6 +43,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
+#include <type_traits>
 
 #include "gemm_tile.h"
 
@@ -236,6 +238,8 @@ hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
 
 template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream);
+template <typename T>
+hipError_t launch_blocked(GemmArgs<T> a, bool pointer_form, hipStream_t stream);
 template <typename T, typename TI>
 int staged_run_length(int m, int n, int k, int64_t batch, int min_waves);
 
@@ -314,6 +318,11 @@ inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
 template <typename T, typename TI, int MODE>
 hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
+    // sizes above 16: the sub-blocked kernel (plain types only)
+    if (a.m > 16 || a.n > 16 || a.k > 16) {
+        if constexpr (MODE == 0 && std::is_same<T, TI>::value) return launch_blocked<T>(a, pointer_form, stream);
+        return hipErrorInvalidValue;
+    }
     const int D = size_class(a.m, a.n, a.k);
     a.G = staged_choice<T, TI>(a, pointer_form);
     if (a.G > 0) {
@@ -350,6 +359,12 @@ template <typename T>
 int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
 {
     const auto tf = [](bool b) { return b ? "true" : "false"; };
+    if (a.m > 16 || a.n > 16 || a.k > 16) {
+        const int nkc = (a.k + 15) / 16;
+        const int U = nkc <= 1 ? 1 : (nkc <= 2 || Tr<T>::cplx ? 2 : 4);
+        return snprintf(buf, len, "void sbg::gemm_blocked_kernel<%s, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form), TypeName<T>::s);
+    }
     const int D = size_class(a.m, a.n, a.k);
     const int G = staged_choice<T, T>(a, pointer_form);
     if (G > 0)

@@ -245,7 +245,10 @@ struct TileRegs {
 // together.  The caller's pointers must be valid whenever the tile is live
 // (tiles past the batch carry a valid matrix's pointers with valid = false),
 // except A and B when alpha == 0 or k == 0 (then they are not read).
-template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT, int AS>
+//
+// CALL: every tile loads its C entries (independent tiles); false: only the
+// first (the U tiles are k-chunks of one output block).
+template <typename T, typename TI, int D, int U, bool ACONT, bool BCONT, int AS, bool CALL = true>
 __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                           bool a0, bool b0, TileRegs<T, TI, D, U>& t)
 {
@@ -294,7 +297,7 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
                     t.vb[u][kb] = ld1<TI>((col_ok && L.kk0 + kb < mt.k) ? mt.B + L.ij + (L.kk0 + kb) * mt.ldb : mt.B);
             }
         }
-        if (!b0) {
+        if (!b0 && (CALL || u == 0)) {
             if (M::swap) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
@@ -316,27 +319,110 @@ __device__ __forceinline__ void tile_load(const LaneMat<T, TI, AS> (&mats)[U], c
     }
 }
 
+// MFMA steps of one tile: the lane's op(A) row and op(B) column entries
+// (stored format in va, vb; decoded here, masked to exact zeros outside the
+// matrix or when !live) multiplied into acc_r (and acc_i for complex types).
+// MODE 0: plain; MODE 1: BF16x3 (each binary32 operand split into bf16
+// hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
+template <typename T, typename TI, int MODE, int D, int AS>
+__device__ __forceinline__ void tile_mma(const LaneMat<T, TI, AS>& mt, const LaneGeom<D, typename Tr<T>::R>& L,
+                                         bool live, float a_conj, float b_conj, const TI (&va)[D / 4],
+                                         const TI (&vb)[D / 4], typename Mfma<typename Tr<T>::R>::acc_t& acc_r,
+                                         typename Mfma<typename Tr<T>::R>::acc_t& acc_i)
+{
+    using R = typename Tr<T>::R;
+    using M = Mfma<R>;
+    constexpr bool CPLX = Tr<T>::cplx;
+    constexpr int KB = D / 4;
+    const bool row_ok = L.ij < mt.m;
+    const bool col_ok = L.ij < mt.n;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        // masked entries stay exact zeros (never a NaN from memory)
+        const bool oka = live && row_ok && (L.kk0 + kb) < mt.k;
+        const bool okb = live && col_ok && (L.kk0 + kb) < mt.k;
+        const T da = oka ? dec(va[kb]) : make_val<T>(R(0), R(0));
+        const T db = okb ? dec(vb[kb]) : make_val<T>(R(0), R(0));
+        const R xar = re_of<T>(da), xbr = re_of<T>(db);
+        const R xai = CPLX ? im_of<T>(da) * (R)a_conj : R(0);
+        const R xbi = CPLX ? im_of<T>(db) * (R)b_conj : R(0);
+        if (MODE == 1) {
+            const R ah = (R)round_bf16((float)xar);
+            const R al = (R)round_bf16((float)(xar - ah));
+            const R bh = (R)round_bf16((float)xbr);
+            const R bl = (R)round_bf16((float)(xbr - bh));
+            acc_r = M::run(ah, bh, acc_r);
+            acc_r = M::run(ah, bl, acc_r);
+            acc_r = M::run(al, bh, acc_r);
+        } else if (M::swap) {
+            acc_r = M::run(xbr, xar, acc_r);
+            if (CPLX) {
+                acc_r = M::run(xbi, -xai, acc_r);
+                acc_i = M::run(xbi, xar, acc_i);
+                acc_i = M::run(xbr, xai, acc_i);
+            }
+        } else {
+            acc_r = M::run(xar, xbr, acc_r);
+            if (CPLX) {
+                acc_r = M::run(-xai, xbi, acc_r);
+                acc_i = M::run(xar, xbi, acc_i);
+                acc_i = M::run(xai, xbr, acc_i);
+            }
+        }
+    }
+}
+
+// Epilogue of one tile: C = alpha acc + beta C (cin: the lane's C entries as
+// loaded) for the entries the lane keeps, written back to the matrix.
+template <typename T, typename TI, int D, int AS>
+__device__ __forceinline__ void tile_store(const LaneMat<T, TI, AS>& mt, const LaneGeom<D, typename Tr<T>::R>& L,
+                                           const T& alpha, const T& beta, bool a0, bool b0,
+                                           const typename Mfma<typename Tr<T>::R>::acc_t& acc_r,
+                                           const typename Mfma<typename Tr<T>::R>::acc_t& acc_i, const T (&cin)[4])
+{
+    using R = typename Tr<T>::R;
+    using M = Mfma<R>;
+    constexpr bool CPLX = Tr<T>::cplx;
+    const bool row_ok = L.ij < mt.m;
+    const bool col_ok = L.ij < mt.n;
+    const bool lane_ok = M::swap ? row_ok : col_ok;
+    if (!(mt.valid && lane_ok)) return;
+    // scaled narrow inputs: alpha * sA * sB applied as (alpha sA sB) * acc
+    R ar = re_of<T>(alpha);
+    const R ai = im_of<T>(alpha);
+    const R br = re_of<T>(beta), bi = im_of<T>(beta);
+    if (!CPLX && mt.scale != 1.0f) ar = ar * (R)mt.scale;
+    T out[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        out[r] = axpby<T>(ar, ai, br, bi, a0, b0, acc_r[r], acc_i[r], cin[r]);
+    if (M::swap) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (L.keep[r] && L.orow[r] < mt.n) st1<T>(mt.C + L.ij + L.orow[r] * mt.ldc, out[r]);
+    } else {
+        const auto cb = mt.C + L.ij * mt.ldc;
+        if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
+            vstore<T, 4>(cb + L.orow[0], out);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (L.keep[r] && L.orow[r] < mt.m) st1<T>(cb + L.orow[r], out[r]);
+        }
+    }
+}
+
 // Decode, multiply (MFMA steps) and write back U tiles whose loads were
-// issued by tile_load.  MODE 0: plain; MODE 1: BF16x3 (each binary32 operand
-// split into bf16 hi + lo; hi*hi + hi*lo + lo*hi accumulated in binary32).
+// issued by tile_load.
 template <typename T, typename TI, int MODE, int D, int U, int AS>
 __device__ __forceinline__ void tile_finish(const LaneMat<T, TI, AS> (&mats)[U], const LaneGeom<D, typename Tr<T>::R>& L,
                                             const T& alpha, const T& beta, bool a0, bool b0, float a_conj,
                                             float b_conj, const TileRegs<T, TI, D, U>& t)
 {
-    using R = typename Tr<T>::R;
-    using M = Mfma<R>;
-    using acc_t = typename M::acc_t;
-    constexpr bool CPLX = Tr<T>::cplx;
-    constexpr int KB = D / 4;
-    const R ar_ = re_of<T>(alpha), ai_ = im_of<T>(alpha);
-    const R br_ = re_of<T>(beta), bi_ = im_of<T>(beta);
+    using acc_t = typename Mfma<typename Tr<T>::R>::acc_t;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const LaneMat<T, TI, AS>& mt = mats[u];
-        const bool row_ok = L.ij < mt.m;
-        const bool col_ok = L.ij < mt.n;
-        const bool live = mt.valid && !a0;
         acc_t acc_r = {0, 0, 0, 0};
         acc_t acc_i = {0, 0, 0, 0};
         // The MFMA chain runs whatever alpha is (with alpha == 0 every operand
@@ -344,65 +430,8 @@ __device__ __forceinline__ void tile_finish(const LaneMat<T, TI, AS> (&mats)[U],
         // the accumulator reads below by a block boundary, across which the
         // required wait states were found missing (reads of the last
         // accumulator row returned stale values).
-        {
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                // masked entries stay exact zeros (never a NaN from memory)
-                const bool oka = live && row_ok && (L.kk0 + kb) < mt.k;
-                const bool okb = live && col_ok && (L.kk0 + kb) < mt.k;
-                const T da = oka ? dec(t.va[u][kb]) : make_val<T>(R(0), R(0));
-                const T db = okb ? dec(t.vb[u][kb]) : make_val<T>(R(0), R(0));
-                const R xar = re_of<T>(da), xbr = re_of<T>(db);
-                const R xai = CPLX ? im_of<T>(da) * (R)a_conj : R(0);
-                const R xbi = CPLX ? im_of<T>(db) * (R)b_conj : R(0);
-                if (MODE == 1) {
-                    const R ah = (R)round_bf16((float)xar);
-                    const R al = (R)round_bf16((float)(xar - ah));
-                    const R bh = (R)round_bf16((float)xbr);
-                    const R bl = (R)round_bf16((float)(xbr - bh));
-                    acc_r = M::run(ah, bh, acc_r);
-                    acc_r = M::run(ah, bl, acc_r);
-                    acc_r = M::run(al, bh, acc_r);
-                } else if (M::swap) {
-                    acc_r = M::run(xbr, xar, acc_r);
-                    if (CPLX) {
-                        acc_r = M::run(xbi, -xai, acc_r);
-                        acc_i = M::run(xbi, xar, acc_i);
-                        acc_i = M::run(xbr, xai, acc_i);
-                    }
-                } else {
-                    acc_r = M::run(xar, xbr, acc_r);
-                    if (CPLX) {
-                        acc_r = M::run(-xai, xbi, acc_r);
-                        acc_i = M::run(xar, xbi, acc_i);
-                        acc_i = M::run(xai, xbr, acc_i);
-                    }
-                }
-            }
-        }
-        const bool lane_ok = M::swap ? row_ok : col_ok;
-        if (!(mt.valid && lane_ok)) continue;
-        // scaled narrow inputs: alpha * sA * sB applied as (alpha sA sB) * acc
-        R ar = ar_, ai = ai_;
-        if (!CPLX && mt.scale != 1.0f) ar = ar_ * (R)mt.scale;
-        T out[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            out[r] = axpby<T>(ar, ai, br_, bi_, a0, b0, acc_r[r], acc_i[r], t.cin[u][r]);
-        if (M::swap) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (L.keep[r] && L.orow[r] < mt.n) st1<T>(mt.C + L.ij + L.orow[r] * mt.ldc, out[r]);
-        } else {
-            const auto cb = mt.C + L.ij * mt.ldc;
-            if (M::rows_contig && L.keep[0] && (L.orow[0] + 3) < mt.m) {
-                vstore<T, 4>(cb + L.orow[0], out);
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (L.keep[r] && L.orow[r] < mt.m) st1<T>(cb + L.orow[r], out[r]);
-            }
-        }
+        tile_mma<T, TI, MODE, D, AS>(mt, L, mt.valid && !a0, a_conj, b_conj, t.va[u], t.vb[u], acc_r, acc_i);
+        tile_store<T, TI, D, AS>(mt, L, alpha, beta, a0, b0, acc_r, acc_i, t.cin[u]);
     }
 }
 

@@ -80,9 +80,28 @@ def test_invalid_arguments_rejected_in_order(prefix, kw, pos):
 
 
 @pytest.mark.parametrize("prefix", "sdcz")
-def test_sizes_above_16_not_supported(prefix):
-    assert call_strided(prefix, m=17, lda=17, ldc=17, sC=17 * 4) == sbg.SBG_NOT_SUPPORTED
-    assert call_strided(prefix, k=17, ldb=17) == sbg.SBG_NOT_SUPPORTED
+def test_sizes_above_16_accepted_by_plain_forms(prefix):
+    """Plain S/D/C/Z forms take any size (sub-blocked kernel): m = 17 or k = 40
+    passes validation; alpha = 0, beta = 1 makes it a quick return, so nothing
+    is launched on the fake addresses."""
+    L = sbg.load()
+    f = getattr(L, f"sbg_{prefix}gemm_strided_batched")
+    one, z = scal(prefix, 1.0), scal(prefix, 0.0)
+    assert f(b"N", b"N", 17, 4, 4, vp(z), None, 17, 68, None, 4, 16, vp(one), 1, 17, 68, 5, None) == sbg.SBG_OK
+    assert f(b"N", b"N", 4, 4, 40, vp(z), None, 4, 160, None, 40, 160, vp(one), 1, 4, 16, 5, None) == sbg.SBG_OK
+    # an invalid argument is still found first
+    assert f(b"N", b"N", 17, 4, 4, vp(z), None, 16, 68, None, 4, 16, vp(one), 1, 17, 68, 5, None) == \
+        sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == 8
+
+
+def test_sizes_above_16_not_supported_by_mixed_precision_form():
+    L = sbg.load()
+    one = scal("s", 1.0)
+    f = L.sbg_gemm_strided_batched_ex
+    # fake, never dereferenced A/B/C; F32 inputs, plain mode
+    st = f(b"N", b"N", 17, 4, 4, vp(one), 1, 17, 68, None, 1, 4, 16, None, vp(one), 1, 17, 68, 5, 0, 0, None)
+    assert st == sbg.SBG_NOT_SUPPORTED
 
 
 @pytest.mark.parametrize("prefix", "sdcz")
