@@ -1,4 +1,5 @@
-"""CPU oracle for batched small-matrix GEMM -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for batched small-matrix GEMM (and, in oracle.blas, batched GEMV
+and TRSM) -- TEST INFRASTRUCTURE ONLY.
 
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may import
 this package.  The product path (paper_1304_7053_amd) never imports it.
