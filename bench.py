@@ -191,7 +191,7 @@ def main():
         for name, fn in (("small_batch", sec_small_batch), ("complex", sec_complex_sweep),
                          ("varsize_precision", sec_varsize_modes), ("fem", sec_fem_chain),
                          ("fixed_operand", sec_fixed_operand), ("batch_sweep", sec_batch_sweep),
-                         ("large_sizes", sec_large_sizes)):
+                         ("large_sizes", sec_large_sizes), ("blas_routines", sec_blas_routines)):
             try:
                 secondary[name] = fn(stream)
             except Exception as e:  # a secondary failure must not hide the primary line
@@ -587,6 +587,47 @@ def sec_large_sizes(stream):
                                                "gflops": round(2.0 * n ** 3 * N / t / 1e9, 1),
                                                "hbm_frac": round(4.0 * esz * el / t / HBM_PEAK, 4)}
             del A, B, C
+    return out
+
+
+def sec_blas_routines(stream):
+    """Batched GEMV and TRSM in the strided interface (formulated on batched
+    GEMM, the paper's outlook): GEMV y = 1.5 op(A) x - 0.5 y with A 16 x 16,
+    N = 10^6, ops N and T; TRSM op(A) X = 1.5 B with A 16 x 16 lower, 16
+    right-hand sides, N = 200,000, and a blocked order-64 case (N = 20,000).
+    HBM bytes: GEMV A + x + y read + y written; TRSM the triangle of A + B
+    read + B written."""
+    import torch
+
+    from paper_1304_7053_amd import sbg
+    flush = torch.empty(128 * 1024 * 1024, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(13047053 + 9)
+    out = {}
+    for tname, tdt, esz in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        N, m, n = 1_000_000, 16, 16
+        A = torch.rand(N * m * n, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+        x = torch.rand(N * n, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+        y = torch.rand(N * m, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+        for trans in "NT":
+            call = lambda: sbg.gemv_strided(trans, m, n, 1.5, A, m, m * n, x, 1, n, -0.5, y, 1, m, N)  # noqa: E731
+            t = _time_calls(call, 7, flush)
+            byts = esz * N * (m * n + n + 2 * m)
+            out[f"gemv_{tname}_16x16_{trans}"] = {"N": N, "us": round(t * 1e6, 1),
+                                                 "gflops": round(2.0 * m * n * N / t / 1e9, 1),
+                                                 "hbm_frac": round(byts / t / HBM_PEAK, 4)}
+        del A, x, y
+        for s, N in ((16, 200_000), (64, 20_000)):
+            A = torch.rand(N * s * s, generator=gen, device="cuda", dtype=tdt) / s
+            A.view(N, s, s).diagonal(dim1=1, dim2=2).add_(2.0)
+            B = torch.rand(N * s * 16, generator=gen, device="cuda", dtype=tdt) * 2 - 1
+            call = lambda: sbg.trsm_strided("L", "L", "N", "N", s, 16, 1.5, A, s, s * s, B, s, s * 16, N)  # noqa: E731
+            t = _time_calls(call, 7, flush)
+            byts = esz * N * (s * (s + 1) // 2 + 2 * s * 16)
+            out[f"trsm_{tname}_LLNN_{s}x16"] = {"N": N, "us": round(t * 1e6, 1),
+                                               "gflops": round(1.0 * s * s * 16 * N / t / 1e9, 1),
+                                               "hbm_frac": round(byts / t / HBM_PEAK, 4)}
+            del A, B
     return out
 
 

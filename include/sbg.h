@@ -219,6 +219,65 @@ sbg_status_t sbg_quantize_e4m3_vbatched(const int* d_rows, const int* d_cols, in
     const float* const* Xarray, const int* d_ldx, unsigned char* const* Qarray, const int* d_ldq, float* scales,
     int64_t batch_count, void* stream);
 
+/* ---- other BLAS routines in the same strided interface ----------------------
+ * The paper proposes its second-leading-dimension interface for other BLAS
+ * routines, formulated in terms of batched GEMM (Sec. 9).  Both routines
+ * below follow reference-BLAS semantics per matrix, on column-major storage
+ * with 64-bit strides between consecutive matrices / vectors of the batch.
+ *
+ * GEMV: y_p <- alpha op(A_p) x_p + beta y_p, A_p m x n, op in N, T, C (R is
+ * rejected); x_p has n entries for N (m for T, C), y_p the other count.
+ * Vector entry i of x_p is x[stridex p + incx i] (likewise y).  Runs as one
+ * batched GEMM call: y as an m' x 1 matrix when incy == 1, otherwise
+ * y^T = alpha x^T op(A)^T + beta y^T with y^T a 1 x m' matrix of leading
+ * dimension incy.  Positions: 1 trans, 2 m, 3 n, 4 alpha, 5 A, 6 lda
+ * (>= max(1, m)), 7 strideA (>= 0), 8 x, 9 incx (>= 1; negative increments
+ * are not supported), 10 stridex (>= 0), 11 beta, 12 y, 13 incy (>= 1),
+ * 14 stridey (>= 0, and >= (len_y - 1) incy + 1 when batch_count > 1: output
+ * vectors may not overlap), 15 batch_count, 16 stream.  Quick returns as in
+ * BLAS: m == 0 or n == 0 leaves y unchanged; alpha == 0 and beta == 1 (host
+ * mode) too.  alpha == 0 does not read A or x; beta == 0 does not read y.
+ *
+ * TRSM: side 'L' solves op(A_p) X_p = alpha B_p (A_p m x m), side 'R'
+ * X_p op(A_p) = alpha B_p (A_p n x n); B_p is m x n and is overwritten by X_p.
+ * uplo 'U'/'L' selects the triangle of A_p that is read; diag 'U' takes the
+ * diagonal as ones without reading it, 'N' reads it.  The triangular order
+ * s (m for L, n for R) may be any size: up to 16 one substitution kernel
+ * (one thread per right-hand-side vector); above 16, B is scaled by alpha,
+ * then 16 x 16 diagonal blocks are solved by that kernel and the rest of B is
+ * updated by batched GEMM calls (several launches on `stream`).  alpha == 0
+ * sets B to zero without reading A (host mode; in device mode with s > 16 A
+ * is still read).  No singularity check: a zero diagonal entry gives Inf/NaN
+ * as in BLAS.  Positions: 1 side, 2 uplo, 3 transa (N, T, C), 4 diag, 5 m,
+ * 6 n, 7 alpha, 8 A, 9 lda (>= max(1, s)), 10 strideA (>= 0), 11 B, 12 ldb
+ * (>= max(1, m)), 13 strideB (>= ldb * n when batch_count > 1),
+ * 14 batch_count, 15 stream.  Quick return: m == 0, n == 0 or
+ * batch_count == 0. */
+sbg_status_t sbg_sgemv_strided_batched(char trans, int m, int n, const float* alpha, const float* A, int lda,
+    int64_t strideA, const float* x, int incx, int64_t stridex, const float* beta, float* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream);
+sbg_status_t sbg_dgemv_strided_batched(char trans, int m, int n, const double* alpha, const double* A, int lda,
+    int64_t strideA, const double* x, int incx, int64_t stridex, const double* beta, double* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream);
+sbg_status_t sbg_cgemv_strided_batched(char trans, int m, int n, const sbg_cfloat* alpha, const sbg_cfloat* A,
+    int lda, int64_t strideA, const sbg_cfloat* x, int incx, int64_t stridex, const sbg_cfloat* beta,
+    sbg_cfloat* y, int incy, int64_t stridey, int64_t batch_count, void* stream);
+sbg_status_t sbg_zgemv_strided_batched(char trans, int m, int n, const sbg_cdouble* alpha, const sbg_cdouble* A,
+    int lda, int64_t strideA, const sbg_cdouble* x, int incx, int64_t stridex, const sbg_cdouble* beta,
+    sbg_cdouble* y, int incy, int64_t stridey, int64_t batch_count, void* stream);
+sbg_status_t sbg_strsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const float* alpha, const float* A, int lda, int64_t strideA, float* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream);
+sbg_status_t sbg_dtrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const double* alpha, const double* A, int lda, int64_t strideA, double* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream);
+sbg_status_t sbg_ctrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const sbg_cfloat* alpha, const sbg_cfloat* A, int lda, int64_t strideA, sbg_cfloat* B, int ldb,
+    int64_t strideB, int64_t batch_count, void* stream);
+sbg_status_t sbg_ztrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const sbg_cdouble* alpha, const sbg_cdouble* A, int lda, int64_t strideA, sbg_cdouble* B, int ldb,
+    int64_t strideB, int64_t batch_count, void* stream);
+
 /* ---- library state ----------------------------------------------------------
  * sbg_set_scalar_mode: where alpha/beta live for calls made later by the
  *   calling thread (thread-local; default SBG_SCALAR_HOST).  In DEVICE mode the

@@ -369,6 +369,251 @@ sbg_status_t vbatched(char ta, char tb, const int* dm, const int* dn, const int*
 
 bool ab_type_ok(int t) { return t >= 0 && t <= 3; }
 
+template <typename T> T real_val(double v);
+template <> float real_val<float>(double v) { return (float)v; }
+template <> double real_val<double>(double v) { return v; }
+template <> float2 real_val<float2>(double v) { return make_float2((float)v, 0.f); }
+template <> double2 real_val<double2>(double v) { return make_double2(v, 0.0); }
+
+// Batched GEMV, y_p <- alpha op(A_p) x_p + beta y_p, in the paper's strided
+// interface (its Sec. 9 proposes the interface for other BLAS routines,
+// formulated on batched GEMM), run as one batched GEMM:
+//  * incy == 1: y is an m' x 1 matrix C; x the k x 1 matrix B (incx == 1) or
+//    the transpose of a 1 x k matrix with leading dimension incx;
+//  * incy > 1: y^T = alpha x^T op(A)^T + beta y^T, a 1 x m' matrix with
+//    leading dimension incy; op(A)^T is A read with the other op ('T' for
+//    'N', 'N' for 'T', conjugated 'N' for 'C').
+// Positions: 1 trans, 2 m, 3 n, 4 alpha, 5 A, 6 lda, 7 strideA, 8 x, 9 incx,
+// 10 stridex, 11 beta, 12 y, 13 incy, 14 stridey, 15 batch_count.
+template <typename T>
+sbg_status_t gemv(char trans, int m, int n, const typename Scal<T>::api_t* alpha, const void* A, int lda,
+                  int64_t sA, const void* x, int incx, int64_t sx, const typename Scal<T>::api_t* beta, void* y,
+                  int incy, int64_t sy, int64_t batch, void* stream)
+{
+    tl_last_invalid = 0;
+    const Op op = decode_op(trans);
+    if (op == OP_BAD || op == OP_R) return reject(1);
+    if (m < 0) return reject(2);
+    if (n < 0) return reject(3);
+    if (!alpha) return reject(4);
+    const bool host = tl_scalar_mode == SBG_SCALAR_HOST;
+    T al{}, be{};
+    if (host) al = Scal<T>::get(alpha);
+    const int rows = op == OP_N ? m : n, cols = op == OP_N ? n : m;
+    const bool nonempty = m > 0 && n > 0 && batch > 0;
+    const bool need_ax = !host || !Scal<T>::zero(al);
+    if (need_ax && nonempty && !A) return reject(5);
+    if (lda < (m > 1 ? m : 1)) return reject(6);
+    if (sA < 0) return reject(7);
+    if (need_ax && nonempty && !x) return reject(8);
+    if (incx < 1) return reject(9);
+    if (sx < 0) return reject(10);
+    if (!beta) return reject(11);
+    if (nonempty && !y) return reject(12);
+    if (incy < 1) return reject(13);
+    // output vectors may not overlap
+    if (sy < 0 || (batch > 1 && rows > 0 && sy < (int64_t)(rows - 1) * incy + 1)) return reject(14);
+    if (batch < 0) return reject(15);
+    // BLAS quick returns: an empty A leaves y untouched
+    if (!nonempty) return SBG_OK;
+    if (host) {
+        be = Scal<T>::get(beta);
+        if (Scal<T>::zero(al) && Scal<T>::one(be)) return SBG_OK;
+    }
+    GemmArgs<T> g{};
+    g.k = cols;
+    if (incy == 1) {
+        g.m = rows;
+        g.n = 1;
+        g.A = A;
+        g.lda = lda;
+        g.strideA = sA;
+        g.a_trans = op != OP_N;
+        g.a_conj = op == OP_C ? -1.f : 1.f;
+        g.B = x;
+        g.b_trans = incx != 1;
+        g.ldb = incx != 1 ? incx : (cols > 1 ? cols : 1);
+        g.strideB = sx;
+        g.b_conj = 1.f;
+        g.ldc = rows;
+    } else {
+        g.m = 1;
+        g.n = rows;
+        g.A = x;
+        g.a_trans = incx == 1;
+        g.lda = incx == 1 ? (cols > 1 ? cols : 1) : incx;
+        g.strideA = sx;
+        g.a_conj = 1.f;
+        g.B = A;
+        g.ldb = lda;
+        g.strideB = sA;
+        g.b_trans = op == OP_N;
+        g.b_conj = op == OP_C ? -1.f : 1.f;
+        g.ldc = incy;
+    }
+    g.C = static_cast<T*>(y);
+    g.strideC = sy;
+    g.batch = batch;
+    if (host) {
+        g.alpha = al;
+        g.beta = be;
+    } else {
+        g.alpha_dev = reinterpret_cast<const T*>(alpha);
+        g.beta_dev = reinterpret_cast<const T*>(beta);
+    }
+    return launch_plain<T>(g, false, stream);
+}
+
+// Batched TRSM in the strided interface: side L solves op(A_p) X_p =
+// alpha B_p, side R X_p op(A_p) = alpha B_p, with A_p triangular (uplo) and
+// unit or non-unit diagonal; X_p overwrites B_p.  Formulated on batched GEMM
+// as the paper suggests (Sec. 9): with the triangular order s <= 16 one
+// launch of the substitution kernel; larger s is cut into diagonal blocks of
+// 16 -- B is first scaled by alpha (a GEMM with k = 0), then each diagonal
+// block is solved by the substitution kernel and the remaining rows (side L)
+// or columns (side R) of B are updated by one batched GEMM with the solved
+// block (alpha = -1, beta = 1).
+// Positions: 1 side, 2 uplo, 3 transa, 4 diag, 5 m, 6 n, 7 alpha, 8 A, 9 lda,
+// 10 strideA, 11 B, 12 ldb, 13 strideB, 14 batch_count.
+template <typename T>
+sbg_status_t trsm(char side, char uplo, char transa, char diag, int m, int n,
+                  const typename Scal<T>::api_t* alpha, const void* A, int lda, int64_t sA, void* B, int ldb,
+                  int64_t sB, int64_t batch, void* stream)
+{
+    tl_last_invalid = 0;
+    const bool left = side == 'L' || side == 'l';
+    if (!left && side != 'R' && side != 'r') return reject(1);
+    const bool up = uplo == 'U' || uplo == 'u';
+    if (!up && uplo != 'L' && uplo != 'l') return reject(2);
+    const Op op = decode_op(transa);
+    if (op == OP_BAD || op == OP_R) return reject(3);
+    const bool unit = diag == 'U' || diag == 'u';
+    if (!unit && diag != 'N' && diag != 'n') return reject(4);
+    if (m < 0) return reject(5);
+    if (n < 0) return reject(6);
+    if (!alpha) return reject(7);
+    const bool host = tl_scalar_mode == SBG_SCALAR_HOST;
+    T al{};
+    if (host) al = Scal<T>::get(alpha);
+    const int s = left ? m : n;
+    const bool nonempty = m > 0 && n > 0 && batch > 0;
+    if (nonempty && (!host || !Scal<T>::zero(al)) && !A) return reject(8);
+    if (lda < (s > 1 ? s : 1)) return reject(9);
+    if (sA < 0) return reject(10);
+    if (nonempty && !B) return reject(11);
+    if (ldb < (m > 1 ? m : 1)) return reject(12);
+    if (sB < 0 || (batch > 1 && sB < (int64_t)ldb * n)) return reject(13);
+    if (batch < 0) return reject(14);
+    if (!nonempty) return SBG_OK;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    T* Bp = static_cast<T*>(B);
+    const T* Ap = static_cast<const T*>(A);
+    // M, the matrix applied to each right-hand-side vector: op(A) for side L,
+    // op(A)^T for side R; M(i, l) = A[l + lda i] when eff_trans
+    const bool op_lower = (!up) == (op == OP_N);
+    const bool lower = left ? op_lower : !op_lower;
+    const bool eff_trans = left ? op != OP_N : op == OP_N;
+    const bool conj = op == OP_C;
+    TrsmArgs<T> t{};
+    t.lower = lower;
+    t.eff_trans = eff_trans;
+    t.conj = conj;
+    t.unit = unit;
+    t.lda = lda;
+    t.strideA = sA;
+    t.strideB = sB;
+    t.batch = batch;
+    t.nv = left ? n : m;
+    t.vec_elem = left ? 1 : ldb;     // element i of a vector
+    t.vec_step = left ? ldb : 1;     // the next vector
+    if (s <= 16) {
+        t.size = s;
+        t.A = Ap;
+        t.B = Bp;
+        if (host) t.alpha = al;
+        else t.alpha_dev = reinterpret_cast<const T*>(alpha);
+        return launch_trsm_small<T>(t, st) == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+    }
+    // B <- alpha B: C = alpha * 0 + beta C with k = 0 and beta = the caller's alpha
+    {
+        GemmArgs<T> g{};
+        g.m = m;
+        g.n = n;
+        g.k = 0;
+        g.A = Bp;
+        g.B = Bp;
+        g.lda = ldb;
+        g.ldb = 1;
+        g.ldc = ldb;
+        g.C = Bp;
+        g.strideC = sB;
+        g.batch = batch;
+        g.a_conj = g.b_conj = 1.f;
+        g.alpha = real_val<T>(1.0);
+        if (host) g.beta = al;
+        else g.beta_dev = reinterpret_cast<const T*>(alpha);
+        if (launch_gemm<T>(g, false, st) != hipSuccess) return SBG_HIP_ERROR;
+        if (host && Scal<T>::zero(al)) return SBG_OK;   // B = 0; A not read
+    }
+    const int nb = (s + 15) / 16;
+    for (int q = 0; q < nb; ++q) {
+        const int b = lower ? q : nb - 1 - q;          // block in solve order
+        const int r0 = 16 * b, rs = s - r0 < 16 ? s - r0 : 16;
+        // the diagonal block: M(r0.., r0..) and the vectors' entries r0..
+        t.size = rs;
+        t.A = Ap + r0 + (int64_t)lda * r0;
+        t.B = Bp + (left ? r0 : (int64_t)ldb * r0);
+        t.alpha = real_val<T>(1.0);
+        t.alpha_dev = nullptr;
+        if (launch_trsm_small<T>(t, st) != hipSuccess) return SBG_HIP_ERROR;
+        // the rest of the vectors' entries: after the block (lower M) or before it
+        const int e0 = lower ? r0 + rs : 0;
+        const int ecnt = lower ? s - (r0 + rs) : r0;
+        if (ecnt == 0) continue;
+        // M(e0.., r0..) as a stored sub-matrix: element (i, l) at
+        // A[(e0 + i) + lda (r0 + l)], or A[(r0 + l) + lda (e0 + i)] when eff_trans
+        const T* Mblk = eff_trans ? Ap + r0 + (int64_t)lda * e0 : Ap + e0 + (int64_t)lda * r0;
+        GemmArgs<T> g{};
+        g.batch = batch;
+        g.alpha = real_val<T>(-1.0);
+        g.beta = real_val<T>(1.0);
+        g.strideA = left ? sA : sB;
+        g.strideB = left ? sB : sA;
+        g.strideC = sB;
+        g.ldc = ldb;
+        g.k = rs;
+        if (left) {
+            // B(e0.., :) -= M(e0.., r0..) X(r0.., :)
+            g.m = ecnt;
+            g.n = n;
+            g.A = Mblk;
+            g.lda = lda;
+            g.a_trans = eff_trans;
+            g.a_conj = conj ? -1.f : 1.f;
+            g.B = Bp + r0;
+            g.ldb = ldb;
+            g.b_trans = false;
+            g.b_conj = 1.f;
+            g.C = Bp + e0;
+        } else {
+            // B(:, e0..) -= X(:, r0..) M(e0.., r0..)^T
+            g.m = m;
+            g.n = ecnt;
+            g.A = Bp + (int64_t)ldb * r0;
+            g.lda = ldb;
+            g.a_trans = false;
+            g.a_conj = 1.f;
+            g.B = Mblk;
+            g.ldb = lda;
+            g.b_trans = !eff_trans;
+            g.b_conj = conj ? -1.f : 1.f;
+            g.C = Bp + (int64_t)ldb * e0;
+        }
+        if (launch_gemm<T>(g, false, st) != hipSuccess) return SBG_HIP_ERROR;
+    }
+    return SBG_OK;
+}
+
 }  // namespace
 }  // namespace sbg
 
@@ -376,6 +621,70 @@ using sbg::pointers;
 using sbg::strided;
 
 extern "C" {
+
+sbg_status_t sbg_sgemv_strided_batched(char trans, int m, int n, const float* alpha, const float* A, int lda,
+    int64_t strideA, const float* x, int incx, int64_t stridex, const float* beta, float* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream)
+{
+    return sbg::gemv<float>(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey,
+                            batch_count, stream);
+}
+
+sbg_status_t sbg_strsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const float* alpha, const float* A, int lda, int64_t strideA, float* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream)
+{
+    return sbg::trsm<float>(side, uplo, transa, diag, m, n, alpha, A, lda, strideA, B, ldb, strideB, batch_count,
+                            stream);
+}
+
+sbg_status_t sbg_dgemv_strided_batched(char trans, int m, int n, const double* alpha, const double* A, int lda,
+    int64_t strideA, const double* x, int incx, int64_t stridex, const double* beta, double* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream)
+{
+    return sbg::gemv<double>(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey,
+                            batch_count, stream);
+}
+
+sbg_status_t sbg_dtrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const double* alpha, const double* A, int lda, int64_t strideA, double* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream)
+{
+    return sbg::trsm<double>(side, uplo, transa, diag, m, n, alpha, A, lda, strideA, B, ldb, strideB, batch_count,
+                            stream);
+}
+
+sbg_status_t sbg_cgemv_strided_batched(char trans, int m, int n, const sbg_cfloat* alpha, const sbg_cfloat* A, int lda,
+    int64_t strideA, const sbg_cfloat* x, int incx, int64_t stridex, const sbg_cfloat* beta, sbg_cfloat* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream)
+{
+    return sbg::gemv<float2>(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey,
+                            batch_count, stream);
+}
+
+sbg_status_t sbg_ctrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const sbg_cfloat* alpha, const sbg_cfloat* A, int lda, int64_t strideA, sbg_cfloat* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream)
+{
+    return sbg::trsm<float2>(side, uplo, transa, diag, m, n, alpha, A, lda, strideA, B, ldb, strideB, batch_count,
+                            stream);
+}
+
+sbg_status_t sbg_zgemv_strided_batched(char trans, int m, int n, const sbg_cdouble* alpha, const sbg_cdouble* A, int lda,
+    int64_t strideA, const sbg_cdouble* x, int incx, int64_t stridex, const sbg_cdouble* beta, sbg_cdouble* y, int incy,
+    int64_t stridey, int64_t batch_count, void* stream)
+{
+    return sbg::gemv<double2>(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey,
+                            batch_count, stream);
+}
+
+sbg_status_t sbg_ztrsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,
+    const sbg_cdouble* alpha, const sbg_cdouble* A, int lda, int64_t strideA, sbg_cdouble* B, int ldb, int64_t strideB,
+    int64_t batch_count, void* stream)
+{
+    return sbg::trsm<double2>(side, uplo, transa, diag, m, n, alpha, A, lda, strideA, B, ldb, strideB, batch_count,
+                            stream);
+}
 
 sbg_status_t sbg_sgemm_strided_batched(char ta, char tb, int m, int n, int k, const float* alpha,
     const float* A, int lda, int64_t sA, const float* B, int ldb, int64_t sB, const float* beta,

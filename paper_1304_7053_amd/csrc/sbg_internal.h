@@ -108,4 +108,27 @@ struct QuantArgs {
 
 hipError_t launch_quant_e4m3(const QuantArgs& q, bool var, hipStream_t stream);
 
+// Small triangular solves (size <= 16) of a strided batch, one right-hand-side
+// vector per thread: element e of vector v of matrix p is
+// B[strideB p + vec_step v + vec_elem e]; the triangular matrix M acts on
+// those vectors, M(i, l) = A_p[l + lda i] when eff_trans, else A_p[i + lda l],
+// conjugated when conj; lower selects forward substitution; unit takes the
+// diagonal as ones.  Solves M x = alpha b in place for every vector.
+template <typename T>
+struct TrsmArgs {
+    int size;                     // order of M (<= 16)
+    int64_t nv;                   // vectors per matrix
+    bool lower, eff_trans, conj, unit;
+    const T* A;
+    int64_t lda, strideA;
+    T* B;
+    int64_t vec_elem, vec_step, strideB;
+    int64_t batch;
+    T alpha;
+    const T* alpha_dev;           // device scalar, or null for `alpha`
+};
+
+template <typename T>
+hipError_t launch_trsm_small(const TrsmArgs<T>& a, hipStream_t stream);
+
 }  // namespace sbg

@@ -39,6 +39,9 @@ EXPORTS = [
     "sbg_vbatched_workspace_size", "sbg_sgemm_vbatched", "sbg_dgemm_vbatched", "sbg_cgemm_vbatched",
     "sbg_zgemm_vbatched", "sbg_gemm_strided_batched_ex", "sbg_gemm_vbatched_ex",
     "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched", "sbg_set_tuning", "sbg_get_tuning",
+    "sbg_sgemv_strided_batched", "sbg_dgemv_strided_batched", "sbg_cgemv_strided_batched",
+    "sbg_zgemv_strided_batched", "sbg_strsm_strided_batched", "sbg_dtrsm_strided_batched",
+    "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched",
 ]
 
 
@@ -96,6 +99,13 @@ def load():
     lib.sbg_quantize_e4m3_strided_batched.restype = c_int
     lib.sbg_quantize_e4m3_vbatched.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp, vp, i64, vp]
     lib.sbg_quantize_e4m3_vbatched.restype = c_int
+    for p in "sdcz":
+        f = getattr(lib, f"sbg_{p}gemv_strided_batched")
+        f.argtypes = [c_char, c_int, c_int, vp, vp, c_int, i64, vp, c_int, i64, vp, vp, c_int, i64, i64, vp]
+        f.restype = c_int
+        f = getattr(lib, f"sbg_{p}trsm_strided_batched")
+        f.argtypes = [c_char, c_char, c_char, c_char, c_int, c_int, vp, vp, c_int, i64, vp, c_int, i64, i64, vp]
+        f.restype = c_int
     lib.sbg_set_tuning.argtypes = [ctypes.c_char_p, c_int]
     lib.sbg_set_tuning.restype = c_int
     lib.sbg_get_tuning.argtypes = [ctypes.c_char_p]
@@ -173,6 +183,47 @@ def gemm_batched(transa, transb, m, n, k, alpha, Aptrs, lda, Bptrs, ldb, beta, C
            batch, _stream(stream))
     if check:
         _check(st, "gemm_batched")
+    return st
+
+
+def gemv_strided(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey, batch,
+                 stream=None, check=True):
+    """Batched GEMV y_p <- alpha op(A_p) x_p + beta y_p on flat device tensors
+    (column-major A, vectors with increments); scalars as in gemm_strided."""
+    L = load()
+    dtype = y.dtype
+    f = getattr(L, f"sbg_{_PREFIX[dtype]}gemv_strided_batched")
+    st = _call_scalars(lambda al, be: f(trans.encode(), m, n, al, _dptr(A), lda, strideA, _dptr(x), incx, stridex,
+                                        be, _dptr(y), incy, stridey, batch, _stream(stream)),
+                       alpha, beta, dtype)
+    if check:
+        _check(st, "gemv_strided")
+    return st
+
+
+def trsm_strided(side, uplo, transa, diag, m, n, alpha, A, lda, strideA, B, ldb, strideB, batch, stream=None,
+                 check=True):
+    """Batched TRSM on flat device tensors: side L solves op(A_p) X_p =
+    alpha B_p, side R X_p op(A_p) = alpha B_p; X_p overwrites B_p.  alpha is a
+    Python scalar (host mode) or a 1-element device tensor (device mode)."""
+    L = load()
+    dtype = B.dtype
+    f = getattr(L, f"sbg_{_PREFIX[dtype]}trsm_strided_batched")
+    dev = isinstance(alpha, torch.Tensor)
+    if dev:
+        al = ctypes.c_void_p(alpha.data_ptr())
+        L.sbg_set_scalar_mode(SCALAR_DEVICE)
+    else:
+        buf = _scalar_buf(alpha, dtype)
+        al = ctypes.cast(buf, ctypes.c_void_p)
+    try:
+        st = f(side.encode(), uplo.encode(), transa.encode(), diag.encode(), m, n, al, _dptr(A), lda, strideA,
+               _dptr(B), ldb, strideB, batch, _stream(stream))
+    finally:
+        if dev:
+            L.sbg_set_scalar_mode(SCALAR_HOST)
+    if check:
+        _check(st, "trsm_strided")
     return st
 
 

@@ -195,3 +195,64 @@ def test_vbatched_workspace_validation():
     assert f(*args((1 << 20) + 8, need)) == sbg.SBG_INVALID_VALUE
     assert sbg.last_invalid_arg() == 18
     assert f(*args(1 << 20, need - 1)) == sbg.SBG_WORKSPACE_TOO_SMALL
+
+
+def _gemv(prefix, trans="N", m=4, n=5, alpha=True, A=1, lda=4, sA=20, x=1, incx=1, sx=5, beta=True, y=1, incy=1,
+          sy=4, batch=3):
+    L = sbg.load()
+    f = getattr(L, f"sbg_{prefix}gemv_strided_batched")
+    one, half = scal(prefix, 1.0), scal(prefix, 0.5)
+    return f(trans.encode(), m, n, vp(one) if alpha else None, A, lda, sA, x, incx, sx, vp(half) if beta else None,
+             y, incy, sy, batch, None)
+
+
+@pytest.mark.parametrize("prefix", "sdcz")
+@pytest.mark.parametrize("kw,pos", [
+    (dict(trans="X"), 1), (dict(trans="R"), 1), (dict(m=-1), 2), (dict(n=-1), 3), (dict(alpha=False), 4),
+    (dict(A=None), 5), (dict(lda=3), 6), (dict(sA=-1), 7), (dict(x=None), 8), (dict(incx=0), 9),
+    (dict(incx=-1), 9), (dict(sx=-1), 10), (dict(beta=False), 11), (dict(y=None), 12), (dict(incy=0), 13),
+    (dict(sy=3), 14), (dict(trans="T", incy=2, sy=8), 14), (dict(batch=-1), 15),
+])
+def test_gemv_invalid_arguments_rejected_in_order(prefix, kw, pos):
+    assert _gemv(prefix, **kw) == sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == pos
+
+
+@pytest.mark.parametrize("prefix", "sdcz")
+def test_gemv_quick_returns(prefix):
+    assert _gemv(prefix, m=0, A=None, x=None, y=None) == sbg.SBG_OK
+    assert _gemv(prefix, n=0, A=None, x=None, y=None) == sbg.SBG_OK
+    assert _gemv(prefix, batch=0, A=None, x=None, y=None) == sbg.SBG_OK
+    L = sbg.load()
+    f = getattr(L, f"sbg_{prefix}gemv_strided_batched")
+    z, one = scal(prefix, 0.0), scal(prefix, 1.0)
+    # alpha == 0 and beta == 1: nothing to do, A and x may be null
+    assert f(b"N", 4, 5, vp(z), None, 4, 20, None, 1, 5, vp(one), 1, 1, 4, 3, None) == sbg.SBG_OK
+
+
+def _trsm(prefix, side="L", uplo="U", trans="N", diag="N", m=4, n=3, alpha=True, A=1, lda=4, sA=16, B=1, ldb=4,
+          sB=12, batch=2):
+    L = sbg.load()
+    f = getattr(L, f"sbg_{prefix}trsm_strided_batched")
+    one = scal(prefix, 1.0)
+    return f(side.encode(), uplo.encode(), trans.encode(), diag.encode(), m, n, vp(one) if alpha else None, A, lda,
+             sA, B, ldb, sB, batch, None)
+
+
+@pytest.mark.parametrize("prefix", "sdcz")
+@pytest.mark.parametrize("kw,pos", [
+    (dict(side="X"), 1), (dict(uplo="X"), 2), (dict(trans="R"), 3), (dict(trans="Q"), 3), (dict(diag="X"), 4),
+    (dict(m=-1), 5), (dict(n=-1), 6), (dict(alpha=False), 7), (dict(A=None), 8), (dict(lda=3), 9),
+    (dict(side="R", lda=2), 9), (dict(sA=-1), 10), (dict(B=None), 11), (dict(ldb=3), 12), (dict(sB=11), 13),
+    (dict(batch=-1), 14), (dict(side="X", m=-1), 1),
+])
+def test_trsm_invalid_arguments_rejected_in_order(prefix, kw, pos):
+    assert _trsm(prefix, **kw) == sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == pos
+
+
+@pytest.mark.parametrize("prefix", "sdcz")
+def test_trsm_quick_returns(prefix):
+    assert _trsm(prefix, m=0, A=None, B=None) == sbg.SBG_OK
+    assert _trsm(prefix, n=0, A=None, B=None, sB=0) == sbg.SBG_OK
+    assert _trsm(prefix, batch=0, A=None, B=None) == sbg.SBG_OK
