@@ -7,9 +7,11 @@
 // One thread owns one right-hand-side vector (a column of B for side L, a row
 // for side R) of at most 16 entries, kept in registers, and substitutes
 // through the triangle: forward for a lower M, backward for an upper one.
-// Entries of M are read from memory as they are needed; the threads of one
-// matrix read the same entries at the same time, so each is fetched once per
-// wave from the cache.  alpha = 0 writes zeros and reads neither A nor B.
+// With at least 8 vectors per matrix each work-group first copies its
+// matrices into LDS (trsm_lds_kernel); otherwise entries of M are read from
+// memory as they are needed (trsm_small_kernel), the threads of one matrix
+// reading the same entries together.  alpha = 0 writes zeros and reads
+// neither A nor B.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -132,11 +134,92 @@ __global__ __launch_bounds__(256) void trsm_small_kernel(const TrsmArgs<T> a)
         if (i < s) b[i * ve] = x[i];
 }
 
+// The same solves with each work-group staging its matrices in LDS: MB whole
+// matrices per work-group (MB * nv <= 256 threads, one vector each), the
+// stored size x size blocks copied with consecutive threads on consecutive
+// elements, then every M(i, l) read from LDS (the threads of one matrix read
+// the same word: a broadcast).  Used when a matrix has at least 8 vectors.
+template <typename T, bool LOWER, bool ETRANS>
+__global__ __launch_bounds__(256) void trsm_lds_kernel(const TrsmArgs<T> a, int MB)
+{
+    using R = typename Tr<T>::R;
+    __shared__ T lm[16 * 256];                       // MB * size * size <= 16 * 256 entries
+    const int s = a.size;
+    const int ss = s * s;
+    const int64_t p0 = (int64_t)blockIdx.x * MB;
+    const int cnt = (int)(a.batch - p0 < MB ? a.batch - p0 : MB);
+    const T alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
+    const bool a0 = is_zero(alpha);
+    if (!a0) {
+        for (int e = threadIdx.x; e < cnt * ss; e += 256) {
+            const int q = e / ss, r = e - q * ss;
+            const int col = r / s, row = r - col * s;
+            lm[e] = a.A[(p0 + q) * a.strideA + row + a.lda * col];
+        }
+    }
+    __syncthreads();
+    const int q = threadIdx.x / (int)a.nv;
+    const int v = threadIdx.x - q * (int)a.nv;
+    if (q >= cnt) return;
+    T* b = a.B + (p0 + q) * a.strideB + v * a.vec_step;
+    const int64_t ve = a.vec_elem;
+    if (a0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < s) b[i * ve] = make_val<T>(R(0), R(0));
+        return;
+    }
+    const T* L = lm + q * ss;
+    const auto M = [&](int i, int l) -> T {
+        const T e = ETRANS ? L[l + s * i] : L[i + s * l];
+        return a.conj ? t_conj<T>(e) : e;
+    };
+    T x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        x[i] = i < s ? t_mul<T>(alpha, b[i * ve]) : make_val<T>(R(0), R(0));
+    if (LOWER) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i < s) {
+                T xi = x[i];
+#pragma unroll
+                for (int l = 0; l < i; ++l) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
+                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+            if (i < s) {
+                T xi = x[i];
+#pragma unroll
+                for (int l = i + 1; l < 16; ++l)
+                    if (l < s) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
+                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (i < s) b[i * ve] = x[i];
+}
+
 template <typename T>
 hipError_t launch_trsm_small_impl(const TrsmArgs<T>& a, hipStream_t stream)
 {
     const int64_t threads = a.batch * a.nv;
     if (threads <= 0) return hipSuccess;
+    if (a.nv >= 8 && a.nv <= 256 && a.size >= 1 && a.size <= 16) {
+        int MB = (int)(256 / a.nv);
+        if (MB > 16) MB = 16;
+        const int64_t blocks = (a.batch + MB - 1) / MB;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        auto kern = a.lower ? (a.eff_trans ? trsm_lds_kernel<T, true, true> : trsm_lds_kernel<T, true, false>)
+                            : (a.eff_trans ? trsm_lds_kernel<T, false, true> : trsm_lds_kernel<T, false, false>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, stream, a, MB);
+        return hipGetLastError();
+    }
     const int64_t blocks = (threads + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     auto kern = a.lower ? (a.eff_trans ? trsm_small_kernel<T, true, true> : trsm_small_kernel<T, true, false>)
