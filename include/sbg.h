@@ -228,9 +228,9 @@ sbg_status_t sbg_quantize_e4m3_vbatched(const int* d_rows, const int* d_cols, in
  * GEMV: y_p <- alpha op(A_p) x_p + beta y_p, A_p m x n, op in N, T, C (R is
  * rejected); x_p has n entries for N (m for T, C), y_p the other count.
  * Vector entry i of x_p is x[stridex p + incx i] (likewise y).  Runs as one
- * batched GEMM call: y as an m' x 1 matrix when incy == 1, otherwise
- * y^T = alpha x^T op(A)^T + beta y^T with y^T a 1 x m' matrix of leading
- * dimension incy.  Positions: 1 trans, 2 m, 3 n, 4 alpha, 5 A, 6 lda
+ * batched GEMM call: y as an m' x 1 matrix for op N with incy == 1,
+ * otherwise y^T = alpha x^T op(A)^T + beta y^T with y^T a 1 x m' matrix of
+ * leading dimension incy.  Positions: 1 trans, 2 m, 3 n, 4 alpha, 5 A, 6 lda
  * (>= max(1, m)), 7 strideA (>= 0), 8 x, 9 incx (>= 1; negative increments
  * are not supported), 10 stridex (>= 0), 11 beta, 12 y, 13 incy (>= 1),
  * 14 stridey (>= 0, and >= (len_y - 1) incy + 1 when batch_count > 1: output

@@ -378,11 +378,14 @@ template <> double2 real_val<double2>(double v) { return make_double2(v, 0.0); }
 // Batched GEMV, y_p <- alpha op(A_p) x_p + beta y_p, in the paper's strided
 // interface (its Sec. 9 proposes the interface for other BLAS routines,
 // formulated on batched GEMM), run as one batched GEMM:
-//  * incy == 1: y is an m' x 1 matrix C; x the k x 1 matrix B (incx == 1) or
-//    the transpose of a 1 x k matrix with leading dimension incx;
-//  * incy > 1: y^T = alpha x^T op(A)^T + beta y^T, a 1 x m' matrix with
+//  * op N with incy == 1: y is an m' x 1 matrix C; x the k x 1 matrix B
+//    (incx == 1) or the transpose of a 1 x k matrix with leading dimension
+//    incx;
+//  * otherwise y^T = alpha x^T op(A)^T + beta y^T, a 1 x m' matrix with
 //    leading dimension incy; op(A)^T is A read with the other op ('T' for
-//    'N', 'N' for 'T', conjugated 'N' for 'C').
+//    'N', 'N' for 'T', conjugated 'N' for 'C').  For op T and C this reads A
+//    as the right operand with its k index contiguous (measured faster than
+//    A as a k-contiguous left operand: 0.40 against 0.25 of HBM peak, f32).
 // Positions: 1 trans, 2 m, 3 n, 4 alpha, 5 A, 6 lda, 7 strideA, 8 x, 9 incx,
 // 10 stridex, 11 beta, 12 y, 13 incy, 14 stridey, 15 batch_count.
 template <typename T>
@@ -422,7 +425,7 @@ sbg_status_t gemv(char trans, int m, int n, const typename Scal<T>::api_t* alpha
     }
     GemmArgs<T> g{};
     g.k = cols;
-    if (incy == 1) {
+    if (incy == 1 && op == OP_N) {
         g.m = rows;
         g.n = 1;
         g.A = A;
