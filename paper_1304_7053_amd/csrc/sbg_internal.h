@@ -108,8 +108,8 @@ struct QuantArgs {
 
 hipError_t launch_quant_e4m3(const QuantArgs& q, bool var, hipStream_t stream);
 
-// Small triangular solves (size <= 16) of a strided batch, one right-hand-side
-// vector per thread: element e of vector v of matrix p is
+// Small triangular solves (size <= 16) of a strided batch, one 16-lane row
+// of a wave per matrix: element e of vector v of matrix p is
 // B[strideB p + vec_step v + vec_elem e]; the triangular matrix M acts on
 // those vectors, M(i, l) = A_p[l + lda i] when eff_trans, else A_p[i + lda l],
 // conjugated when conj; lower selects forward substitution; unit takes the

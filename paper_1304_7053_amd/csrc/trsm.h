@@ -4,14 +4,11 @@
 // Sec. 9; the off-diagonal updates of larger solves are batched GEMM calls
 // made by the host, api.cpp).
 //
-// One thread owns one right-hand-side vector (a column of B for side L, a row
-// for side R) of at most 16 entries, kept in registers, and substitutes
-// through the triangle: forward for a lower M, backward for an upper one.
-// With at least 8 vectors per matrix each work-group first copies its
-// matrices into LDS (trsm_lds_kernel); otherwise entries of M are read from
-// memory as they are needed (trsm_small_kernel), the threads of one matrix
-// reading the same entries together.  alpha = 0 writes zeros and reads
-// neither A nor B.
+// One 16-lane row of a wave per matrix: lane r holds row r of the triangular
+// matrix M and entry r of up to 16 right-hand-side vectors at a time, and the
+// substitution runs as 16 steps in which one lane finishes its entries, they
+// are broadcast across the row, and the lanes still to be solved subtract
+// their share.  alpha = 0 writes zeros and reads neither A nor B.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,153 +74,104 @@ template <> __device__ __forceinline__ double2 t_div<double2>(const double2& a, 
 template <> __device__ __forceinline__ float2 t_conj<float2>(const float2& a) { return make_float2(a.x, -a.y); }
 template <> __device__ __forceinline__ double2 t_conj<double2>(const double2& a) { return make_double2(a.x, -a.y); }
 
-template <typename T, bool LOWER, bool ETRANS>
-__global__ __launch_bounds__(256) void trsm_small_kernel(const TrsmArgs<T> a)
+// Width-16 broadcast of lane `src` of each 16-lane row.
+__device__ __forceinline__ float row_bcast(float v, int src) { return __shfl(v, src, 16); }
+__device__ __forceinline__ double row_bcast(double v, int src) { return __shfl(v, src, 16); }
+__device__ __forceinline__ float2 row_bcast(float2 v, int src)
 {
-    using R = typename Tr<T>::R;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= a.batch * a.nv) return;
-    const int64_t p = t / a.nv;
-    const int64_t v = t - p * a.nv;
-    const T alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
-    T* b = a.B + p * a.strideB + v * a.vec_step;
-    const int s = a.size;
-    const int64_t ve = a.vec_elem;
-    if (is_zero(alpha)) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < s) b[i * ve] = make_val<T>(R(0), R(0));
-        return;
-    }
-    const T* A = a.A + p * a.strideA;
-    const int64_t lda = a.lda;
-    // M(i, l); only entries of the triangle (and the diagonal unless unit)
-    // are ever requested
-    const auto M = [&](int i, int l) -> T {
-        const T e = ETRANS ? A[l + lda * i] : A[i + lda * l];
-        return a.conj ? t_conj<T>(e) : e;
-    };
-    T x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-        x[i] = i < s ? t_mul<T>(alpha, b[i * ve]) : make_val<T>(R(0), R(0));
-    if (LOWER) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i < s) {
-                T xi = x[i];
-#pragma unroll
-                for (int l = 0; l < i; ++l) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
-                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            if (i < s) {
-                T xi = x[i];
-#pragma unroll
-                for (int l = i + 1; l < 16; ++l)
-                    if (l < s) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
-                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-        if (i < s) b[i * ve] = x[i];
+    return make_float2(__shfl(v.x, src, 16), __shfl(v.y, src, 16));
+}
+__device__ __forceinline__ double2 row_bcast(double2 v, int src)
+{
+    return make_double2(__shfl(v.x, src, 16), __shfl(v.y, src, 16));
 }
 
-// The same solves with each work-group staging its matrices in LDS: MB whole
-// matrices per work-group (MB * nv <= 256 threads, one vector each), the
-// stored size x size blocks copied with consecutive threads on consecutive
-// elements, then every M(i, l) read from LDS (the threads of one matrix read
-// the same word: a broadcast).  Used when a matrix has at least 8 vectors.
+// Substitution with one 16-lane row per matrix (four matrices per wave): lane
+// r holds row r of M and entry r of up to 16 right-hand-side vectors at a
+// time.  Step i: lane i finishes its entries (times the reciprocal of M(i, i),
+// computed once per lane), they are broadcast across the row, and every lane
+// below i (lower M; above i for upper) subtracts M(r, i) times them.  Loads
+// and stores of one vector entry run across consecutive lanes.
 template <typename T, bool LOWER, bool ETRANS>
-__global__ __launch_bounds__(256) void trsm_lds_kernel(const TrsmArgs<T> a, int MB)
+__global__ __launch_bounds__(256) void trsm_row_kernel(const TrsmArgs<T> a)
 {
     using R = typename Tr<T>::R;
-    __shared__ T lm[16 * 256];                       // MB * size * size <= 16 * 256 entries
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15;
+    const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 + (lane >> 4);
+    if (((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4 >= a.batch) return;   // whole wave past the batch
+    const bool live = p < a.batch;
     const int s = a.size;
-    const int ss = s * s;
-    const int64_t p0 = (int64_t)blockIdx.x * MB;
-    const int cnt = (int)(a.batch - p0 < MB ? a.batch - p0 : MB);
+    const bool row_ok = live && r < s;
     const T alpha = a.alpha_dev ? *a.alpha_dev : a.alpha;
-    const bool a0 = is_zero(alpha);
-    if (!a0) {
-        for (int e = threadIdx.x; e < cnt * ss; e += 256) {
-            const int q = e / ss, r = e - q * ss;
-            const int col = r / s, row = r - col * s;
-            lm[e] = a.A[(p0 + q) * a.strideA + row + a.lda * col];
-        }
-    }
-    __syncthreads();
-    const int q = threadIdx.x / (int)a.nv;
-    const int v = threadIdx.x - q * (int)a.nv;
-    if (q >= cnt) return;
-    T* b = a.B + (p0 + q) * a.strideB + v * a.vec_step;
-    const int64_t ve = a.vec_elem;
-    if (a0) {
+    const T zero = make_val<T>(R(0), R(0));
+    const int64_t pe = live ? p : a.batch - 1;
+    T* bm = a.B + pe * a.strideB;
+    const int64_t ve = a.vec_elem, vs = a.vec_step;
+    if (is_zero(alpha)) {
+        for (int64_t c0 = 0; c0 < a.nv; c0 += 16) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < s) b[i * ve] = make_val<T>(R(0), R(0));
+            for (int v = 0; v < 16; ++v)
+                if (row_ok && c0 + v < a.nv) bm[(c0 + v) * vs + r * ve] = zero;
+        }
         return;
     }
-    const T* L = lm + q * ss;
-    const auto M = [&](int i, int l) -> T {
-        const T e = ETRANS ? L[l + s * i] : L[i + s * l];
-        return a.conj ? t_conj<T>(e) : e;
-    };
-    T x[16];
+    // row r of M (the triangle's part of it) and the reciprocal of M(r, r)
+    const T* Am = a.A + pe * a.strideA;
+    T mr[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        x[i] = i < s ? t_mul<T>(alpha, b[i * ve]) : make_val<T>(R(0), R(0));
-    if (LOWER) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i < s) {
-                T xi = x[i];
-#pragma unroll
-                for (int l = 0; l < i; ++l) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
-                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
-            }
+    for (int l = 0; l < 16; ++l) {
+        const bool need = row_ok && l < s && (LOWER ? l < r : l > r);
+        T e = zero;
+        if (need) {
+            e = ETRANS ? Am[l + a.lda * r] : Am[r + a.lda * l];
+            if (a.conj) e = t_conj<T>(e);
         }
-    } else {
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-            if (i < s) {
-                T xi = x[i];
-#pragma unroll
-                for (int l = i + 1; l < 16; ++l)
-                    if (l < s) xi = t_sub<T>(xi, t_mul<T>(M(i, l), x[l]));
-                x[i] = a.unit ? xi : t_div<T>(xi, M(i, i));
-            }
-        }
+        mr[l] = e;
     }
+    T inv = make_val<T>(R(1), R(0));
+    if (!a.unit && row_ok) {
+        T d = Am[r + a.lda * r];
+        if (a.conj) d = t_conj<T>(d);
+        inv = t_div<T>(make_val<T>(R(1), R(0)), d);
+    }
+    for (int64_t c0 = 0; c0 < a.nv; c0 += 16) {
+        const int nvc = a.nv - c0 < 16 ? (int)(a.nv - c0) : 16;
+        T x[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        if (i < s) b[i * ve] = x[i];
+        for (int v = 0; v < 16; ++v)
+            x[v] = (row_ok && v < nvc) ? t_mul<T>(alpha, bm[(c0 + v) * vs + r * ve]) : zero;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = LOWER ? q : 15 - q;
+            if (i < s) {
+                const bool mine = r == i;
+                const bool below = LOWER ? r > i : r < i;
+                const T m = mr[i];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    if (v < nvc) {
+                        if (mine) x[v] = t_mul<T>(x[v], inv);
+                        const T xi = row_bcast(x[v], i);
+                        if (below) x[v] = t_sub<T>(x[v], t_mul<T>(m, xi));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            if (row_ok && v < nvc) bm[(c0 + v) * vs + r * ve] = x[v];
+    }
 }
 
 template <typename T>
 hipError_t launch_trsm_small_impl(const TrsmArgs<T>& a, hipStream_t stream)
 {
-    const int64_t threads = a.batch * a.nv;
-    if (threads <= 0) return hipSuccess;
-    if (a.nv >= 8 && a.nv <= 256 && a.size >= 1 && a.size <= 16) {
-        int MB = (int)(256 / a.nv);
-        if (MB > 16) MB = 16;
-        const int64_t blocks = (a.batch + MB - 1) / MB;
-        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        auto kern = a.lower ? (a.eff_trans ? trsm_lds_kernel<T, true, true> : trsm_lds_kernel<T, true, false>)
-                            : (a.eff_trans ? trsm_lds_kernel<T, false, true> : trsm_lds_kernel<T, false, false>);
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, stream, a, MB);
-        return hipGetLastError();
-    }
-    const int64_t blocks = (threads + 255) / 256;
+    if (a.batch <= 0 || a.nv <= 0) return hipSuccess;
+    const int64_t blocks = (a.batch + 15) / 16;   // 16 matrices per 256-thread work-group
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    auto kern = a.lower ? (a.eff_trans ? trsm_small_kernel<T, true, true> : trsm_small_kernel<T, true, false>)
-                        : (a.eff_trans ? trsm_small_kernel<T, false, true> : trsm_small_kernel<T, false, false>);
+    auto kern = a.lower ? (a.eff_trans ? trsm_row_kernel<T, true, true> : trsm_row_kernel<T, true, false>)
+                        : (a.eff_trans ? trsm_row_kernel<T, false, true> : trsm_row_kernel<T, false, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
