@@ -243,7 +243,7 @@ sbg_status_t sbg_quantize_e4m3_vbatched(const int* d_rows, const int* d_cols, in
  * uplo 'U'/'L' selects the triangle of A_p that is read; diag 'U' takes the
  * diagonal as ones without reading it, 'N' reads it.  The triangular order
  * s (m for L, n for R) may be any size: up to 16 one substitution kernel
- * (one thread per right-hand-side vector); above 16, B is scaled by alpha,
+ * (one 16-lane row of a wave per matrix); above 16, B is scaled by alpha,
  * then 16 x 16 diagonal blocks are solved by that kernel and the rest of B is
  * updated by batched GEMM calls (several launches on `stream`).  alpha == 0
  * sets B to zero without reading A (host mode; in device mode with s > 16 A
