@@ -6,9 +6,10 @@
 //
 // One 16-lane row of a wave per matrix: lane r holds row r of the triangular
 // matrix M and entry r of up to 16 right-hand-side vectors at a time, and the
-// substitution runs as 16 steps in which one lane finishes its entries, they
-// are broadcast across the row, and the lanes still to be solved subtract
-// their share.  alpha = 0 writes zeros and reads neither A nor B.
+// substitution runs as 16 steps in which the entries of one lane are final,
+// they are broadcast across the row, and the lanes still to be solved
+// subtract their share (rows are scaled by the reciprocal of their diagonal
+// first).  alpha = 0 writes zeros and reads neither A nor B.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -88,10 +89,10 @@ __device__ __forceinline__ double2 row_bcast(double2 v, int src)
 
 // Substitution with one 16-lane row per matrix (four matrices per wave): lane
 // r holds row r of M and entry r of up to 16 right-hand-side vectors at a
-// time.  Step i: lane i finishes its entries (times the reciprocal of M(i, i),
-// computed once per lane), they are broadcast across the row, and every lane
-// below i (lower M; above i for upper) subtracts M(r, i) times them.  Loads
-// and stores of one vector entry run across consecutive lanes.
+// time, both scaled by the reciprocal of M(r, r) (computed once per lane).
+// Step i: lane i's entries are final; they are broadcast across the row, and
+// every lane below i (lower M; above i for upper) subtracts M(r, i) times
+// them.  Loads and stores of one vector entry run across consecutive lanes.
 template <typename T, bool LOWER, bool ETRANS>
 __global__ __launch_bounds__(256) void trsm_row_kernel(const TrsmArgs<T> a)
 {
@@ -129,35 +130,44 @@ __global__ __launch_bounds__(256) void trsm_row_kernel(const TrsmArgs<T> a)
         }
         mr[l] = e;
     }
+    // row r scaled by 1 / M(r, r) once: the system becomes unit-diagonal, so a
+    // step only broadcasts a finished entry and subtracts its multiples
     T inv = make_val<T>(R(1), R(0));
     if (!a.unit && row_ok) {
         T d = Am[r + a.lda * r];
         if (a.conj) d = t_conj<T>(d);
         inv = t_div<T>(make_val<T>(R(1), R(0)), d);
+#pragma unroll
+        for (int l = 0; l < 16; ++l) mr[l] = t_mul<T>(inv, mr[l]);
     }
+    const T ainv = t_mul<T>(alpha, inv);
     for (int64_t c0 = 0; c0 < a.nv; c0 += 16) {
         const int nvc = a.nv - c0 < 16 ? (int)(a.nv - c0) : 16;
         T x[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-            x[v] = (row_ok && v < nvc) ? t_mul<T>(alpha, bm[(c0 + v) * vs + r * ve]) : zero;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int i = LOWER ? q : 15 - q;
-            if (i < s) {
-                const bool mine = r == i;
-                const bool below = LOWER ? r > i : r < i;
-                const T m = mr[i];
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    if (v < nvc) {
-                        if (mine) x[v] = t_mul<T>(x[v], inv);
-                        const T xi = row_bcast(x[v], i);
-                        if (below) x[v] = t_sub<T>(x[v], t_mul<T>(m, xi));
-                    }
-                }
-            }
+            x[v] = (row_ok && v < nvc) ? t_mul<T>(ainv, bm[(c0 + v) * vs + r * ve]) : zero;
+        // one substitution step for the vectors 0..NV-1 of the chunk
+#define SBG_TRSM_STEPS(NV)                                                          \
+        _Pragma("unroll") for (int q = 0; q < 16; ++q) {                            \
+            const int i = LOWER ? q : 15 - q;                                       \
+            if (i < s) {                                                            \
+                const bool below = LOWER ? r > i : r < i;                           \
+                const T m = mr[i];                                                  \
+                _Pragma("unroll") for (int v = 0; v < 16; ++v) {                    \
+                    if (v < (NV)) {                                                 \
+                        const T xi = row_bcast(x[v], i);                            \
+                        if (below) x[v] = t_sub<T>(x[v], t_mul<T>(m, xi));          \
+                    }                                                               \
+                }                                                                   \
+            }                                                                       \
         }
+        if (nvc == 16) {
+            SBG_TRSM_STEPS(16)   // whole chunks: no per-vector test
+        } else {
+            SBG_TRSM_STEPS(nvc)
+        }
+#undef SBG_TRSM_STEPS
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             if (row_ok && v < nvc) bm[(c0 + v) * vs + r * ve] = x[v];
