@@ -78,14 +78,14 @@ class Case:
         j = np.arange(self.n)[None, None, :]
         return flat[p * self.sC + i + j * self.ldc]
 
-    def oracle(self, idx=None, A=None, B=None, C=None):
+    def oracle(self, idx=None, A=None, B=None, C=None, ext=True):
         idx = np.arange(self.batch) if idx is None else np.asarray(idx, dtype=np.int64)
         A = self.A if A is None else A
         B = self.B if B is None else B
         C = self.C if C is None else C
         args = (self.ta, self.tb, self.m, self.n, self.k, self.alpha, A, idx * self.sA, self.lda,
                 B, idx * self.sB, self.ldb, self.beta, C, idx * self.sC, self.ldc, len(idx))
-        hi, lo, offO, _, _ = oracle.gemm_general(*args, ext=True)
+        hi, lo, offO, _, _ = oracle.gemm_general(*args, ext=ext)
         bnd, _ = oracle.bound_general(*args)
         cplx = np.dtype(self.dtype).kind == "c"
         cnt = len(idx)

@@ -106,20 +106,55 @@ def test_alpha_zero_and_beta_zero_special_cases(gpu_lib, dtype):
         assert np.all(c3.unpack(out3) == 0)
 
 
-@pytest.mark.parametrize("dtype", [np.float32, np.complex64], ids=lambda d: np.dtype(d).name)
-def test_integer_data_bit_exact(gpu_lib, dtype):
+def _pointer_run(c, g):
+    """Run a Case through the pointer-array form (matrix pointers of its
+    strided buffers, in a shuffled order); returns the flat C buffer."""
+    esz = np.dtype(c.dtype).itemsize
+    dA, dB, dC = to_dev(c.A), to_dev(c.B), to_dev(c.C)
+    perm = g.permutation(c.batch)
+    pa = torch.tensor(dA.data_ptr() + perm * c.sA * esz, dtype=torch.int64, device="cuda")
+    pb = torch.tensor(dB.data_ptr() + perm * c.sB * esz, dtype=torch.int64, device="cuda")
+    pc = torch.tensor(dC.data_ptr() + perm * c.sC * esz, dtype=torch.int64, device="cuda")
+    sbg.gemm_batched(c.ta, c.tb, c.m, c.n, c.k, c.alpha, pa, c.lda, pb, c.ldb, c.beta, pc, c.ldc, c.batch, dC.dtype)
+    torch.cuda.synchronize()
+    return from_dev(dC)
+
+
+@pytest.mark.parametrize("form", ["strided", "pointer"])
+@pytest.mark.parametrize("dtype", ALL, ids=lambda d: np.dtype(d).name)
+def test_integer_data_bit_exact(gpu_lib, dtype, form):
     """Entries in {-3..3}, dyadic alpha and beta: every partial result is exact
-    in the working precision, so GPU and oracle agree bit for bit."""
+    in the working precision, so GPU and oracle agree bit for bit (-0 == +0),
+    for the four real op pairs of the size sweep, in both batch forms."""
     g = inputs.rng(205)
     al, be = scalars(dtype)
     for s in (2, 5, 8, 11, 16):
         for ops in ("NN", "NT", "TN", "TT"):
-            say(f"integer {np.dtype(dtype).name} {ops} n={s}")
+            say(f"integer {form} {np.dtype(dtype).name} {ops} n={s}")
             c = Case(dtype, ops[0], ops[1], s, s, s, 3001, al, be, g, dist="int")
-            got = c.unpack(c.run_gpu())
+            got = c.unpack(c.run_gpu() if form == "strided" else _pointer_run(c, g))
             ref, lo, _ = c.oracle()
             assert not np.any(lo)
             assert np.array_equal(got.astype(ref.dtype), ref)
+
+
+@pytest.mark.parametrize("dtype", REAL, ids=lambda d: np.dtype(d).name)
+def test_integer_data_full_size_bit_exact(gpu_lib, dtype):
+    """The integer variant of the size sweep at its full size: N = 100,000,
+    square n = 2..16, NN/NT/TN/TT, alpha = 1.5, beta = -0.5, entries in
+    {-3..3}; every matrix of every call equals the oracle bit for bit (its
+    binary64 evaluation of integer data is exact)."""
+    N = 100_000
+    g = inputs.rng(2, salt=7)
+    for s in range(2, 17):
+        c = Case(dtype, "N", "N", s, s, s, N, 1.5, -0.5, g, dist="int")
+        for ops in ("NN", "NT", "TN", "TT"):
+            c.ta, c.tb = ops[0], ops[1]
+            say(f"integer full-size {np.dtype(dtype).name} {ops} n={s} N={N}")
+            got = c.unpack(c.run_gpu())
+            ref, lo, _ = c.oracle(ext=False)
+            assert not np.any(lo)
+            assert np.array_equal(got.astype(np.float64), ref), (ops, s)
 
 
 @pytest.mark.parametrize("dtype", ALL, ids=lambda d: np.dtype(d).name)

@@ -152,3 +152,32 @@ def test_trsm_order_and_triangle_mistakes_fail():
     other, _, _ = blas.trsm("L", "U", "N", "N", m, n, 1.0, A, lda, sA, B, ldb, sB, 1)
     trans, _, _ = blas.trsm("L", "L", "T", "N", m, n, 1.0, A, lda, sA, B, ldb, sB, 1)
     assert not np.allclose(good, other) and not np.allclose(good, trans)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.complex128])
+@pytest.mark.parametrize("side", "LR")
+def test_trsm_residual_rejects_wrong_solutions(dtype, side):
+    """The backward-error check that accepts GPU TRSM results must reject
+    what a broken solver would return: B itself (nothing solved), the
+    solution of the other triangle, the solution of the other op, and a
+    solution with one entry off by a relative 1e-6 -- each ratio far above
+    the acceptance level 4 (s + 1) u, while the true solution sits below it."""
+    g = inputs.rng(506)
+    m, n, batch = 6, 5, 4
+    A, lda, sA, B, ldb, sB = _tri_case(g, dtype, side, m, n, batch)
+    alpha = complex(0.75, -0.5) if np.dtype(dtype).kind == "c" else 1.25
+    size = m if side == "L" else n
+    accept = 4 * (size + 1) * 2.0 ** -53 * (2 if np.dtype(dtype).kind == "c" else 1)
+    args = (side, "L", "N", "N", m, n, alpha, A, lda, sA, B, ldb, sB)
+    hi, lo, _ = blas.trsm(*args, batch)
+    good = hi + lo
+    assert np.all(blas.trsm_residual(*args, good, batch) <= accept)
+    unsolved = np.stack([B[p * sB + np.arange(m)[:, None] + ldb * np.arange(n)[None, :]] for p in range(batch)])
+    assert np.all(blas.trsm_residual(*args, unsolved, batch) > 1e-3)
+    h2, l2, _ = blas.trsm(side, "U", "N", "N", m, n, alpha, A, lda, sA, B, ldb, sB, batch)
+    assert np.all(blas.trsm_residual(*args, h2 + l2, batch) > 1e-3)
+    h3, l3, _ = blas.trsm(side, "L", "T", "N", m, n, alpha, A, lda, sA, B, ldb, sB, batch)
+    assert np.all(blas.trsm_residual(*args, h3 + l3, batch) > 1e-3)
+    nudged = good.copy()
+    nudged[:, 2, 1] *= 1 + 1e-6
+    assert np.all(blas.trsm_residual(*args, nudged, batch) > 1e3 * accept)
