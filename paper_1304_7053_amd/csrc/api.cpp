@@ -54,7 +54,7 @@ int resident_blocks_per_cu(const void* kernel)
 Tuning& tuning_mut()
 {
     static Tuning t = [] {
-        Tuning v{4, 16, 2, 2048, 8192, false};
+        Tuning v{4, 16, 2, 2048, 8192, false, 0};
         if (const char* e = std::getenv("SBG_WG_PER_CU")) {
             int x = std::atoi(e);
             if (x >= 1 && x <= 32) v.wg_per_cu = x;
@@ -68,6 +68,10 @@ Tuning& tuning_mut()
             if (x >= 0 && x <= 2) v.staged = x;
         }
         if (const char* e = std::getenv("SBG_PIPELINE")) v.pipeline = std::atoi(e) != 0;
+        if (const char* e = std::getenv("SBG_PATH")) {
+            int x = std::atoi(e);
+            if (x >= 0 && x <= 2) v.path = x;
+        }
         if (const char* e = std::getenv("SBG_TILE_BYTES")) {
             int x = std::atoi(e);
             if (x >= 256 && x <= (1 << 20)) v.tile_bytes = x;
@@ -949,6 +953,10 @@ int sbg_set_tuning(const char* key, int value)
     } else if (k == "pipeline") {
         old = t.pipeline ? 1 : 0;
         t.pipeline = value != 0;
+    } else if (k == "path") {
+        if (value < 0 || value > 2) return -1;
+        old = t.path;
+        t.path = value;
     } else {
         return -1;
     }
@@ -966,6 +974,7 @@ int sbg_get_tuning(const char* key)
     if (k == "tile_bytes") return t.tile_bytes;
     if (k == "tile_bytes16") return t.tile_bytes16;
     if (k == "pipeline") return t.pipeline ? 1 : 0;
+    if (k == "path") return t.path;
     return -1;
 }
 

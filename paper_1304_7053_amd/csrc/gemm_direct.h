@@ -239,6 +239,8 @@ hipError_t launch_variant(GemmArgs<T> a, hipStream_t stream)
 template <typename T, typename TI, int MODE, int D, bool ACONT, bool BCONT>
 hipError_t launch_staged(GemmArgs<T> a, hipStream_t stream);
 template <typename T>
+hipError_t launch_team(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream);
+template <typename T>
 hipError_t launch_blocked(GemmArgs<T> a, bool pointer_form, hipStream_t stream);
 template <typename T, typename TI>
 int staged_run_length(int m, int n, int k, int64_t batch, int min_waves);
@@ -313,8 +315,46 @@ inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
     return staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
 }
 
-// Strided / pointer-array dispatch: packed strided batches go through the
-// LDS-staged kernel (when enabled), everything else through the direct one.
+// Team kernel geometry (gemm_team.h).  Elements per 16-byte vector:
+template <typename T> struct TeamVec { static constexpr int V = 16 / (int)sizeof(T); };
+
+// Lanes per team: one per column of C and of op(B) (n), one per stored
+// column of A (k columns for op N/R, m for T/C) and of B (k for op T/C).
+__host__ __device__ inline int team_size(int m, int n, int k, bool a_trans)
+{
+    int ts = n > k ? n : k;
+    if (a_trans && m > ts) ts = m;
+    return ts < 1 ? 1 : ts;
+}
+
+// Vector columns when every column the call loads or stores holds at least
+// one 16-byte vector: C's and (op N/R) A's columns have m elements, B's (op
+// N/R) and A's (op T/C) k, B's (op T/C) n.
+template <typename T>
+inline bool team_vec(const GemmArgs<T>& a)
+{
+    constexpr int V = TeamVec<T>::V;
+    const bool kused = a.k > 0;
+    return a.m >= V && (!kused || a.k >= V || (!a.a_trans && a.b_trans)) && (!kused || !a.b_trans || a.n >= V);
+}
+
+// Sizes <= 8 of the plain types: the team kernel (gemm_team.h) or the MFMA
+// tile kernels?  Measured on the MI355X (N = 100,000, square): the team
+// kernel is ahead for every size <= 8 except 8-byte and larger elements at
+// 7 and 8, where the MFMA tiles are full enough to win.
+template <typename T>
+inline bool team_choice(const GemmArgs<T>& a)
+{
+    const int path = tuning().path;
+    if (path == 1) return false;
+    if (path == 2) return true;
+    const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
+    return !(sizeof(T) >= 8 && mx >= 7);
+}
+
+// Strided / pointer-array dispatch: sizes <= 8 through the team kernel (when
+// chosen), packed strided batches through the LDS-staged kernel (when
+// enabled), everything else through the direct one.
 template <typename T, typename TI, int MODE>
 hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
@@ -324,6 +364,8 @@ hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
         return hipErrorInvalidValue;
     }
     const int D = size_class(a.m, a.n, a.k);
+    if constexpr (MODE == 0 && std::is_same<T, TI>::value)
+        if (D <= 8 && team_choice<T>(a)) return launch_team<T>(a, pointer_form, stream);
     a.G = staged_choice<T, TI>(a, pointer_form);
     if (a.G > 0) {
         if (D == 4) return launch_staged_ops<T, TI, MODE, 4>(a, stream);
@@ -366,6 +408,11 @@ int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
                         TypeName<T>::s, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form), TypeName<T>::s);
     }
     const int D = size_class(a.m, a.n, a.k);
+    if (D <= 8 && team_choice<T>(a)) {
+        return snprintf(buf, len, "void sbg::gemm_team_kernel<%s, %d, %s, %s, %s, %s>(sbg::GemmArgs<%s>)",
+                        TypeName<T>::s, D, tf(!a.a_trans), tf(!a.b_trans), tf(team_vec(a)), tf(pointer_form),
+                        TypeName<T>::s);
+    }
     const int G = staged_choice<T, T>(a, pointer_form);
     if (G > 0)
         return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %s, 0, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",

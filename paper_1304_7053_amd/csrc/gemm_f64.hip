@@ -2,6 +2,7 @@
 #include "gemm_vbatched.h"
 #include "gemm_staged.h"
 #include "gemm_blocked.h"
+#include "gemm_team.h"
 #include "trsm.h"
 
 SBG_INSTANTIATE_GEMM(double)

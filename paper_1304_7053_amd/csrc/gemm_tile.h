@@ -149,6 +149,10 @@ __device__ __forceinline__ typename SpacePtr<X, AS>::type in_space(X* p)
 
 // Epilogue of one entry: alpha * acc + beta * c (real or complex), with the
 // special cases alpha == 0 (acc unused) and beta == 0 (c unused).
+// a b + c in the precision of R (no promotion of binary32 operands).
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ T axpby(typename Tr<T>::R ar, typename Tr<T>::R ai, typename Tr<T>::R br,
                                    typename Tr<T>::R bi, bool a0, bool b0, typename Tr<T>::R accr,
@@ -163,17 +167,17 @@ __device__ __forceinline__ T axpby(typename Tr<T>::R ar, typename Tr<T>::R ai, t
         else if (b0)
             o = ar * accr;
         else
-            o = __builtin_fma(ar, accr, br * cr);
+            o = fma_r(ar, accr, br * cr);
         return make_val<T>(o, R(0));
     }
     R tr = 0, ti = 0;
     if (!b0) {
-        tr = __builtin_fma(br, cr, -(bi * ci));
-        ti = __builtin_fma(br, ci, bi * cr);
+        tr = fma_r(br, cr, -(bi * ci));
+        ti = fma_r(br, ci, bi * cr);
     }
     if (!a0) {
-        tr = __builtin_fma(ar, accr, __builtin_fma(-ai, acci, tr));
-        ti = __builtin_fma(ar, acci, __builtin_fma(ai, accr, ti));
+        tr = fma_r(ar, accr, fma_r(-ai, acci, tr));
+        ti = fma_r(ar, acci, fma_r(ai, accr, ti));
     }
     return make_val<T>(tr, ti);
 }

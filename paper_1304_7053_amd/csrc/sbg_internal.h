@@ -37,6 +37,7 @@ struct GemmArgs {
     const float* scaleB;
     int64_t batch;
     int64_t xcd_chunk;             // consecutive work units per XCD run (set by the launcher)
+    int64_t blocks;                // work-groups with work in a one-shot grid (set by the launcher)
     int G;                         // matrices per wave step of the LDS-staged kernel
     // variable-size form: per-matrix sizes and leading dimensions, workspace
     const int* dm;
@@ -62,6 +63,7 @@ struct Tuning {
     int tile_bytes;    // per-wave bytes in flight per step, size classes 4 and 8
     int tile_bytes16;  // the same for size class 16, per 4-byte element size (scaled by sizeof(T) / 4)
     bool pipeline;     // issue the next group's loads before computing the current one
+    int path;          // sizes <= 8: 0 automatic, 1 MFMA tile kernels only, 2 team kernel whenever it applies
 };
 const Tuning& tuning();
 Tuning& tuning_mut();

@@ -1,8 +1,9 @@
 """Parity of every kernel path the launcher can select, not only the default
-one: the LDS-staged kernel for packed strided batches, the prefetching
-(pipelined) direct kernel, the extreme tile unrolls (one tile per group, and
-the largest unroll the size class allows) and a persistent grid of one
-work-group per CU walking many work units.  Each path reruns the parity cases
+one: the team kernel for sizes <= 8 wherever it applies, the MFMA tile
+kernels for those sizes (with the LDS-staged kernel for packed strided
+batches, the prefetching (pipelined) direct kernel, the extreme tile unrolls
+-- one tile per group, and the largest unroll the size class allows -- and a
+persistent grid of one work-group per CU walking many work units).  Each path reruns the parity cases
 of the default path (same oracle, same 4 max(k,1) u acceptance test), and the
 kernel name the library reports confirms which kernel ran."""
 import numpy as np
@@ -15,11 +16,12 @@ from gpu_util import say
 pytestmark = pytest.mark.gpu
 
 PATHS = {
-    "staged": dict(staged=1, pipeline=0),
-    "pipelined": dict(staged=0, pipeline=1),
-    "unroll1": dict(staged=0, pipeline=0, tile_bytes=256, tile_bytes16=256),
-    "unrollmax": dict(staged=0, pipeline=0, tile_bytes=1 << 20, tile_bytes16=1 << 20),
-    "onewg": dict(staged=0, pipeline=0, wg_per_cu=1, xcd_chunk=1),
+    "team": dict(path=2),
+    "staged": dict(staged=1, pipeline=0, path=1),
+    "pipelined": dict(staged=0, pipeline=1, path=1),
+    "unroll1": dict(staged=0, pipeline=0, tile_bytes=256, tile_bytes16=256, path=1),
+    "unrollmax": dict(staged=0, pipeline=0, tile_bytes=1 << 20, tile_bytes16=1 << 20, path=1),
+    "onewg": dict(staged=0, pipeline=0, wg_per_cu=1, xcd_chunk=1, path=1),
 }
 
 
@@ -34,7 +36,9 @@ def test_path_parity(gpu_lib, path, dtype):
     with sbg.tuned(**PATHS[path]):
         name = _kernel(dtype, 8, 100_000)
         say(f"path {path} {np.dtype(dtype).name}: {name}")
-        if path == "staged":
+        if path == "team":
+            assert "gemm_team_kernel" in name
+        elif path == "staged":
             assert "gemm_staged_kernel" in name
         else:
             assert "gemm_mfma_kernel" in name
@@ -48,7 +52,7 @@ def test_path_parity(gpu_lib, path, dtype):
         P.test_device_scalar_mode(gpu_lib, dtype)
 
 
-@pytest.mark.parametrize("path", ["staged", "pipelined"])
+@pytest.mark.parametrize("path", ["team", "staged", "pipelined"])
 @pytest.mark.parametrize("dtype", P.REAL, ids=lambda d: np.dtype(d).name)
 def test_path_full_size(gpu_lib, path, dtype):
     """The N = 100,000 size sweep through the alternative paths."""
@@ -56,11 +60,11 @@ def test_path_full_size(gpu_lib, path, dtype):
         P.test_full_size_square_sweep(gpu_lib, dtype)
 
 
-@pytest.mark.parametrize("path", ["staged", "pipelined"])
+@pytest.mark.parametrize("path", ["team", "staged", "pipelined"])
 def test_path_integer_bit_exact(gpu_lib, path):
     with sbg.tuned(**PATHS[path]):
-        for dtype in (np.float32, np.complex64):
-            P.test_integer_data_bit_exact(gpu_lib, dtype)
+        for dtype in P.ALL:
+            P.test_integer_data_bit_exact(gpu_lib, dtype, "strided")
 
 
 @pytest.mark.parametrize("path", ["staged", "pipelined"])
