@@ -204,6 +204,26 @@ sbg_status_t sbg_gemm_vbatched_ex(char transa, char transb, const int* d_m, cons
     float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type,
     sbg_compute_mode_t mode, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- variable-size mixed precision without a workspace argument ------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, and harnesses that forbid allocation.  Same
+ * arguments, semantics and positions 1-21 as sbg_gemm_vbatched_ex, with the
+ * workspace taken from a scratch array the library keeps in device memory
+ * (one copy per GPU, resident until the process ends), so the call performs
+ * no allocation of any kind.
+ *   batch_count above SBG_NOALLOC_MAX_BATCH gives SBG_WORKSPACE_TOO_SMALL.
+ *   The scratch is shared by every call on a GPU and keeps the last call's
+ *   contents (its counters are cleared by each call): calls that overlap on
+ *   one GPU (other streams, other threads) race and must be serialised by
+ *   the caller.  The rejected-matrix count is not returned (it lives in the
+ *   shared scratch).  Position 22 is the stream. */
+#define SBG_NOALLOC_MAX_BATCH 262144
+sbg_status_t sbg_gemm_vbatched_ex_noalloc(char transa, char transb, const int* d_m, const int* d_n,
+    const int* d_k, int max_m, int max_n, int max_k, const float* alpha, const void* const* Aarray,
+    const int* d_lda, const float* scaleA, const void* const* Barray, const int* d_ldb, const float* scaleB,
+    const float* beta, float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type,
+    sbg_compute_mode_t mode, void* stream);
+
 /* ---- per-matrix absmax quantisation to FP8 E4M3 -----------------------------
  * For each binary32 matrix X_p (rows x cols <= 16 x 16): s_p = max|X_p| / 448
  * (1 for an all-zero matrix), Q_p = e4m3(X_p / s_p) rounded to nearest even and

@@ -621,6 +621,28 @@ sbg_status_t trsm(char side, char uplo, char transa, char diag, int m, int n,
     return SBG_OK;
 }
 
+// The variable-size mixed-precision call with a given workspace (positions of
+// the workspace arguments in pos).
+sbg_status_t vb_ex(char transa, char transb, const int* d_m, const int* d_n, const int* d_k, int max_m, int max_n,
+                   int max_k, const float* alpha, const void* const* Aarray, const int* d_lda, const float* scaleA,
+                   const void* const* Barray, const int* d_ldb, const float* scaleB, const float* beta,
+                   float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type,
+                   sbg_compute_mode_t mode, void* workspace, size_t workspace_bytes, const VbPos& pos, void* stream)
+{
+    GemmArgs<float> a{};
+    bool launch = false;
+    sbg_status_t st = vb_run<float>(transa, transb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda,
+                                    scaleA, Barray, d_ldb, scaleB, beta, Carray, d_ldc, batch_count, workspace,
+                                    workspace_bytes, pos, a, launch, ab_type == SBG_R_8F_E4M3);
+    if (st != SBG_OK) return st;
+    if (!ab_type_ok((int)ab_type)) return reject(20);
+    if (mode != SBG_MODE_PLAIN && mode != SBG_MODE_BF16X3) return reject(21);
+    if (mode == SBG_MODE_BF16X3 && ab_type != SBG_R_32F) return reject(21);
+    if (!launch) return SBG_OK;
+    hipError_t e = launch_gemm_ex(a, (int)ab_type, (int)mode, 2, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
 }  // namespace
 }  // namespace sbg
 
@@ -804,6 +826,7 @@ sbg_status_t sbg_gemm_strided_batched_ex(char transa, char transb, int m, int n,
     return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
 }
 
+
 sbg_status_t sbg_gemm_vbatched_ex(char transa, char transb, const int* d_m, const int* d_n, const int* d_k,
     int max_m, int max_n, int max_k, const float* alpha, const void* const* Aarray, const int* d_lda,
     const float* scaleA, const void* const* Barray, const int* d_ldb, const float* scaleB, const float* beta,
@@ -812,19 +835,26 @@ sbg_status_t sbg_gemm_vbatched_ex(char transa, char transb, const int* d_m, cons
 {
     // positions: 1-8 as sbg_?gemm_vbatched, 9 alpha 10 Aarray 11 d_lda 12 scaleA 13 Barray 14 d_ldb
     // 15 scaleB 16 beta 17 Carray 18 d_ldc 19 batch_count 20 ab_type 21 mode 22 workspace 23 workspace_bytes
-    sbg::GemmArgs<float> a{};
     static const sbg::VbPos pos = {9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 22, 23};
-    bool launch = false;
-    sbg_status_t st = sbg::vb_run<float>(transa, transb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda,
-                                         scaleA, Barray, d_ldb, scaleB, beta, Carray, d_ldc, batch_count, workspace,
-                                         workspace_bytes, pos, a, launch, ab_type == SBG_R_8F_E4M3);
-    if (st != SBG_OK) return st;
-    if (!sbg::ab_type_ok((int)ab_type)) return sbg::reject(20);
-    if (mode != SBG_MODE_PLAIN && mode != SBG_MODE_BF16X3) return sbg::reject(21);
-    if (mode == SBG_MODE_BF16X3 && ab_type != SBG_R_32F) return sbg::reject(21);
-    if (!launch) return SBG_OK;
-    hipError_t e = sbg::launch_gemm_ex(a, (int)ab_type, (int)mode, 2, reinterpret_cast<hipStream_t>(stream));
-    return e == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+    return sbg::vb_ex(transa, transb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda, scaleA, Barray,
+                      d_ldb, scaleB, beta, Carray, d_ldc, batch_count, ab_type, mode, workspace, workspace_bytes,
+                      pos, stream);
+}
+
+sbg_status_t sbg_gemm_vbatched_ex_noalloc(char transa, char transb, const int* d_m, const int* d_n,
+    const int* d_k, int max_m, int max_n, int max_k, const float* alpha, const void* const* Aarray,
+    const int* d_lda, const float* scaleA, const void* const* Barray, const int* d_ldb, const float* scaleB,
+    const float* beta, float* const* Carray, const int* d_ldc, int64_t batch_count, sbg_datatype_t ab_type,
+    sbg_compute_mode_t mode, void* stream)
+{
+    // the library's scratch replaces the workspace (never null, 256-byte
+    // aligned); a batch above SBG_NOALLOC_MAX_BATCH finds it too small
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    if (sbg::noalloc_scratch(&ws, &ws_bytes) != hipSuccess) return SBG_HIP_ERROR;
+    static const sbg::VbPos pos = {9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 0, 0};
+    return sbg::vb_ex(transa, transb, d_m, d_n, d_k, max_m, max_n, max_k, alpha, Aarray, d_lda, scaleA, Barray,
+                      d_ldb, scaleB, beta, Carray, d_ldc, batch_count, ab_type, mode, ws, ws_bytes, pos, stream);
 }
 
 sbg_status_t sbg_quantize_e4m3_strided_batched(int rows, int cols, const float* X, int ldx, int64_t strideX,

@@ -43,7 +43,7 @@ struct alignas(16) VbRec {
 };
 static_assert(sizeof(VbRec) == 48, "record layout");
 
-inline size_t vbatched_workspace_bytes(int64_t batch)
+constexpr size_t vbatched_workspace_bytes(int64_t batch)
 {
     return (size_t)VB_HEADER_BYTES + 3 * (size_t)(batch > 0 ? batch : 0) * sizeof(VbRec);
 }

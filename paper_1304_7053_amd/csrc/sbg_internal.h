@@ -85,6 +85,11 @@ template <typename T>
 hipError_t launch_vbatched(const GemmArgs<T>& a, hipStream_t stream);
 size_t vb_workspace_bytes(int64_t batch);
 
+// The library's device scratch for the allocation-free variable-size entry
+// point (room for the workspace of SBG_NOALLOC_MAX_BATCH matrices): its
+// device address on the current device (looked up once per device) and size.
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
+
 // Mixed precision on binary32 C: ab_type 0 f32, 1 bf16, 2 f16, 3 e4m3;
 // mode 0 plain, 1 BF16x3 (ab_type 0 only); form 0 strided, 1 pointer, 2 var-size.
 hipError_t launch_gemm_ex(const GemmArgs<float>& a, int ab_type, int mode, int form, hipStream_t stream);

@@ -41,7 +41,7 @@ EXPORTS = [
     "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched", "sbg_set_tuning", "sbg_get_tuning",
     "sbg_sgemv_strided_batched", "sbg_dgemv_strided_batched", "sbg_cgemv_strided_batched",
     "sbg_zgemv_strided_batched", "sbg_strsm_strided_batched", "sbg_dtrsm_strided_batched",
-    "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched",
+    "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched", "sbg_gemm_vbatched_ex_noalloc",
 ]
 
 
@@ -95,6 +95,9 @@ def load():
     lib.sbg_gemm_vbatched_ex.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp, vp, i64, c_int, c_int, vp, ctypes.c_size_t, vp]
     lib.sbg_gemm_vbatched_ex.restype = c_int
+    lib.sbg_gemm_vbatched_ex_noalloc.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp,
+                                                 vp, vp, vp, vp, vp, vp, i64, c_int, c_int, vp]
+    lib.sbg_gemm_vbatched_ex_noalloc.restype = c_int
     lib.sbg_quantize_e4m3_strided_batched.argtypes = [c_int, c_int, vp, c_int, i64, vp, c_int, i64, vp, i64, vp]
     lib.sbg_quantize_e4m3_strided_batched.restype = c_int
     lib.sbg_quantize_e4m3_vbatched.argtypes = [vp, vp, c_int, c_int, vp, vp, vp, vp, vp, i64, vp]
@@ -295,6 +298,25 @@ def gemm_vbatched_ex(transa, transb, dm, dn, dk, max_m, max_n, max_k, alpha, Apt
         alpha, beta, torch.float32)
     if check:
         _check(st, "gemm_vbatched_ex")
+    return st
+
+
+NOALLOC_MAX_BATCH = 262144   # SBG_NOALLOC_MAX_BATCH of include/sbg.h
+
+
+def gemm_vbatched_ex_noalloc(transa, transb, dm, dn, dk, max_m, max_n, max_k, alpha, Aptrs, dlda, scaleA, Bptrs,
+                             dldb, scaleB, beta, Cptrs, dldc, batch, ab_type, mode, stream=None, check=True):
+    """sbg_gemm_vbatched_ex without a workspace: the library's own device
+    scratch serves as the workspace (no allocation; calls on one GPU must not
+    overlap)."""
+    L = load()
+    st = _call_scalars(lambda al, be: L.sbg_gemm_vbatched_ex_noalloc(
+        transa.encode(), transb.encode(), _dptr(dm), _dptr(dn), _dptr(dk), max_m, max_n, max_k, al, _dptr(Aptrs),
+        _dptr(dlda), _dptr(scaleA), _dptr(Bptrs), _dptr(dldb), _dptr(scaleB), be, _dptr(Cptrs), _dptr(dldc), batch,
+        ab_type, mode, _stream(stream)),
+        alpha, beta, torch.float32)
+    if check:
+        _check(st, "gemm_vbatched_ex_noalloc")
     return st
 
 
