@@ -314,24 +314,41 @@ const char* sbg_status_string(sbg_status_t status);
 int sbg_version(void);
 
 /* ---- launch tuning ----------------------------------------------------------
- * Process-wide knobs of the kernel selection and launch shape, for tuning
- * sweeps and A/B comparisons (not thread-safe against concurrent calls; set
- * them before launching).  Keys: "wg_per_cu" (persistent work-groups per CU,
- * 1..32), "xcd_chunk" (consecutive work units per XCD run, >= 1), "staged"
- * (packed strided batches through the LDS-staged kernel: 0 never, 1 always,
- * 2 automatic = real types in the size-16 class, for 4-byte inputs unless m
- * and k are multiples of 4, for 8-byte inputs up to 11 rows/columns; default
- * 2), "tile_bytes"
- * and "tile_bytes16" (per-wave bytes in flight that choose the direct
- * kernel's tile unroll for the size classes 4/8 and 16, 256..2^20; the
- * class-16 budget is for 4-byte elements and scales with the element size),
- * "pipeline" (0/1: prefetch the next tile group in the direct kernel).
- * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED,
- * SBG_TILE_BYTES, SBG_TILE_BYTES16, SBG_PIPELINE set the initial values.
+ * Each call's kernel and launch shape come, in this order, from: knobs set to
+ * a non-automatic value; the tuned table (one entry per type, batch form, op
+ * pair and size max(m, n, k) <= 16, measured by the autotuner
+ * paper_1304_7053_amd/tune.py and read once per process from SBG_TUNE_FILE or
+ * from tuned.json beside the library); built-in rules.
+ * Knobs are process-wide, for tuning sweeps and A/B comparisons (not
+ * thread-safe against concurrent calls; set them before launching).  Keys
+ * (0 = automatic unless stated):
+ *   "wg_per_cu"   persistent grids: work-groups per CU, 0..32 (automatic: 4);
+ *   "xcd_chunk"   consecutive work units per XCD run, >= 0 (automatic: 16);
+ *   "staged"      packed strided batches through the LDS-staged kernel:
+ *                 0 never, 1 always, 2 automatic (default);
+ *   "path"        0 automatic, 1 MFMA tile kernels only, 2 team kernel for
+ *                 sizes <= 8, 3 team kernel also up to 16 (real types);
+ *   "unroll"      tiles per wave step of the direct kernel, 0..8 (a power of
+ *                 two, capped per size class);
+ *   "grid"        work-groups of persistent grids, 0..2^20 (the launch-shape
+ *                 sweep; 0: CUs times wg_per_cu);
+ *   "table"       1 (default) use the tuned table, 0 ignore it;
+ *   "tile_bytes", "tile_bytes16"  per-wave bytes in flight that choose the
+ *                 direct kernel's unroll when neither the knob nor the table
+ *                 does (size classes 4/8 and 16; 256..2^20; the class-16
+ *                 budget is for 4-byte elements and scales with the size);
+ *   "pipeline"    0/1: prefetch the next tile group in the direct kernel.
+ * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED, SBG_PATH,
+ * SBG_UNROLL, SBG_GRID, SBG_TABLE, SBG_TILE_BYTES, SBG_TILE_BYTES16 and
+ * SBG_PIPELINE set the initial values.
  * sbg_set_tuning returns the previous value, or -1 for an unknown key or an
- * out-of-range value (nothing changed); sbg_get_tuning returns the value or -1. */
+ * out-of-range value (nothing changed); sbg_get_tuning returns the value or -1.
+ * sbg_tuned_table_info writes "file=<path> version=<v> entries=<count>" into
+ * buf (loading the table on first use) and returns the number of entries, or
+ * -1 for a null or empty buffer. */
 int sbg_set_tuning(const char* key, int value);
 int sbg_get_tuning(const char* key);
+int sbg_tuned_table_info(char* buf, int buflen);
 
 /* ---- diagnostics --------------------------------------------------------
  * sbg_describe_strided: validates the arguments of a strided call (prefix

@@ -54,32 +54,23 @@ int resident_blocks_per_cu(const void* kernel)
 Tuning& tuning_mut()
 {
     static Tuning t = [] {
-        Tuning v{4, 16, 2, 2048, 8192, false, 0};
-        if (const char* e = std::getenv("SBG_WG_PER_CU")) {
-            int x = std::atoi(e);
-            if (x >= 1 && x <= 32) v.wg_per_cu = x;
-        }
-        if (const char* e = std::getenv("SBG_XCD_CHUNK")) {
-            int x = std::atoi(e);
-            if (x >= 1) v.xcd_chunk = x;
-        }
-        if (const char* e = std::getenv("SBG_STAGED")) {
-            int x = std::atoi(e);
-            if (x >= 0 && x <= 2) v.staged = x;
-        }
+        Tuning v{0, 0, 2, 2048, 8192, false, 0, 0, 0, 1};
+        const auto env = [](const char* name, int lo, int hi, int& dst) {
+            if (const char* e = std::getenv(name)) {
+                const int x = std::atoi(e);
+                if (x >= lo && x <= hi) dst = x;
+            }
+        };
+        env("SBG_WG_PER_CU", 0, 32, v.wg_per_cu);
+        env("SBG_XCD_CHUNK", 0, 1 << 20, v.xcd_chunk);
+        env("SBG_STAGED", 0, 2, v.staged);
+        env("SBG_TILE_BYTES", 256, 1 << 20, v.tile_bytes);
+        env("SBG_TILE_BYTES16", 256, 1 << 20, v.tile_bytes16);
+        env("SBG_PATH", 0, 3, v.path);
+        env("SBG_UNROLL", 0, 8, v.unroll);
+        env("SBG_GRID", 0, 1 << 20, v.grid);
+        env("SBG_TABLE", 0, 1, v.table);
         if (const char* e = std::getenv("SBG_PIPELINE")) v.pipeline = std::atoi(e) != 0;
-        if (const char* e = std::getenv("SBG_PATH")) {
-            int x = std::atoi(e);
-            if (x >= 0 && x <= 2) v.path = x;
-        }
-        if (const char* e = std::getenv("SBG_TILE_BYTES")) {
-            int x = std::atoi(e);
-            if (x >= 256 && x <= (1 << 20)) v.tile_bytes = x;
-        }
-        if (const char* e = std::getenv("SBG_TILE_BYTES16")) {
-            int x = std::atoi(e);
-            if (x >= 256 && x <= (1 << 20)) v.tile_bytes16 = x;
-        }
         return v;
     }();
     return t;
@@ -954,43 +945,44 @@ int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, in
     return st == SBG_OK && buf[0] ? 0 : -1;
 }
 
+namespace {
+struct Knob {
+    const char* name;
+    int lo, hi;
+    int sbg::Tuning::*field;
+};
+const Knob kKnobs[] = {
+    {"wg_per_cu", 0, 32, &sbg::Tuning::wg_per_cu},
+    {"xcd_chunk", 0, 1 << 20, &sbg::Tuning::xcd_chunk},
+    {"staged", 0, 2, &sbg::Tuning::staged},
+    {"tile_bytes", 256, 1 << 20, &sbg::Tuning::tile_bytes},
+    {"tile_bytes16", 256, 1 << 20, &sbg::Tuning::tile_bytes16},
+    {"path", 0, 3, &sbg::Tuning::path},
+    {"unroll", 0, 8, &sbg::Tuning::unroll},
+    {"grid", 0, 1 << 20, &sbg::Tuning::grid},
+    {"table", 0, 1, &sbg::Tuning::table},
+};
+}  // namespace
+
 int sbg_set_tuning(const char* key, int value)
 {
     if (!key) return -1;
     sbg::Tuning& t = sbg::tuning_mut();
     const std::string k(key);
-    int old;
-    if (k == "wg_per_cu") {
-        if (value < 1 || value > 32) return -1;
-        old = t.wg_per_cu;
-        t.wg_per_cu = value;
-    } else if (k == "xcd_chunk") {
-        if (value < 1) return -1;
-        old = t.xcd_chunk;
-        t.xcd_chunk = value;
-    } else if (k == "staged") {
-        if (value < 0 || value > 2) return -1;
-        old = t.staged;
-        t.staged = value;
-    } else if (k == "tile_bytes") {
-        if (value < 256 || value > (1 << 20)) return -1;
-        old = t.tile_bytes;
-        t.tile_bytes = value;
-    } else if (k == "tile_bytes16") {
-        if (value < 256 || value > (1 << 20)) return -1;
-        old = t.tile_bytes16;
-        t.tile_bytes16 = value;
-    } else if (k == "pipeline") {
-        old = t.pipeline ? 1 : 0;
+    if (k == "pipeline") {
+        const int old = t.pipeline ? 1 : 0;
         t.pipeline = value != 0;
-    } else if (k == "path") {
-        if (value < 0 || value > 2) return -1;
-        old = t.path;
-        t.path = value;
-    } else {
-        return -1;
+        return old;
     }
-    return old;
+    for (const Knob& kn : kKnobs) {
+        if (k == kn.name) {
+            if (value < kn.lo || value > kn.hi) return -1;
+            const int old = t.*kn.field;
+            t.*kn.field = value;
+            return old;
+        }
+    }
+    return -1;
 }
 
 int sbg_get_tuning(const char* key)
@@ -998,14 +990,15 @@ int sbg_get_tuning(const char* key)
     if (!key) return -1;
     const sbg::Tuning& t = sbg::tuning();
     const std::string k(key);
-    if (k == "wg_per_cu") return t.wg_per_cu;
-    if (k == "xcd_chunk") return t.xcd_chunk;
-    if (k == "staged") return t.staged;
-    if (k == "tile_bytes") return t.tile_bytes;
-    if (k == "tile_bytes16") return t.tile_bytes16;
     if (k == "pipeline") return t.pipeline ? 1 : 0;
-    if (k == "path") return t.path;
+    for (const Knob& kn : kKnobs)
+        if (k == kn.name) return t.*kn.field;
     return -1;
+}
+
+int sbg_tuned_table_info(char* buf, int buflen)
+{
+    return sbg::tuned_table_info(buf, buflen);
 }
 
 void sbg_set_scalar_mode(sbg_scalar_mode_t mode)

@@ -162,14 +162,16 @@ inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
 {
     const Tuning& tu = tuning();
     int per_cu = resident_per_cu(kernel);
-    if (per_cu > tu.wg_per_cu) per_cu = tu.wg_per_cu;
+    const int want = a.plan_wg > 0 ? a.plan_wg : (tu.wg_per_cu > 0 ? tu.wg_per_cu : 4);
+    if (per_cu > want) per_cu = want;
     const int64_t wg_needed = (units + 3) / 4;
-    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    const int64_t cap = tu.grid > 0 ? (int64_t)tu.grid : (int64_t)device_cu_count() * per_cu;
     int64_t grid = wg_needed < cap ? wg_needed : cap;
     if (grid < 1) grid = 1;
     grid = ((grid + 7) / 8) * 8;
     const int64_t wx = grid / 8 * 4;   // waves per XCD
-    int64_t s = tu.xcd_chunk > 0 ? tu.xcd_chunk : 1;
+    const int xc = a.plan_xcd > 0 ? a.plan_xcd : (tu.xcd_chunk > 0 ? tu.xcd_chunk : 16);
+    int64_t s = xc;
     if (s > wx) s = wx;
     while (wx % s) --s;
     a.xcd_chunk = s;
@@ -211,6 +213,11 @@ template <typename T, int D> struct UMax {
 template <typename T, typename TI, int D>
 inline int choose_unroll(const GemmArgs<T>& a)
 {
+    if (a.plan_unroll > 0) {
+        int U = 1;
+        while (U * 2 <= UMax<T, D>::value && U * 2 <= a.plan_unroll) U *= 2;
+        return U;
+    }
     const int64_t P = 16 / D;
     const int64_t tile = P * ((int64_t)(a.m * a.k + a.k * a.n) * (int64_t)sizeof(TI) +
                               2 * (int64_t)a.m * a.n * (int64_t)sizeof(T));
@@ -294,27 +301,6 @@ hipError_t launch_staged_ops(const GemmArgs<T>& a, hipStream_t stream)
               : launch_staged<T, TI, MODE, D, false, false>(a, stream);
 }
 
-// Matrices per staged run for this call, or 0 to use the direct kernel.
-template <typename T, typename TI>
-inline int staged_choice(const GemmArgs<T>& a, bool pointer_form)
-{
-    const int mode = tuning().staged;
-    if (pointer_form || mode == 0 || !is_packed(a) || a.scaleA) return 0;
-    // Automatic choice (measured): in the 16 class the staged kernel wins
-    // when the direct kernel cannot use whole vectors -- for 4-byte inputs
-    // unless m and k are multiples of 4 (then the k-contiguous operand and C
-    // load as 16-byte vectors), for 8-byte inputs up to 11 rows/columns
-    // (longer f64 rows fill their cache lines directly).  The smaller
-    // classes and the complex types (four real products per step double the
-    // LDS gathers) stay on the direct kernel.
-    if (mode == 2) {
-        const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
-        if (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16) return 0;
-        if (sizeof(TI) >= 8 ? mx > 11 : ((a.m & 3) == 0 && (a.k & 3) == 0)) return 0;
-    }
-    return staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
-}
-
 // Team kernel geometry (gemm_team.h).  Elements per 16-byte vector:
 template <typename T> struct TeamVec { static constexpr int V = 16 / (int)sizeof(T); };
 
@@ -338,36 +324,95 @@ inline bool team_vec(const GemmArgs<T>& a)
     return a.m >= V && (!kused || a.k >= V || (!a.a_trans && a.b_trans)) && (!kused || !a.b_trans || a.n >= V);
 }
 
-// Sizes <= 8 of the plain types: the team kernel (gemm_team.h) or the MFMA
-// tile kernels?  Measured on the MI355X (N = 100,000, square): the team
-// kernel is ahead for every size <= 8 except 8-byte and larger elements at
-// 7 and 8, where the MFMA tiles are full enough to win.
-template <typename T>
-inline bool team_choice(const GemmArgs<T>& a)
+// The built-in rule for the staged kernel (measured): in the 16 class it wins
+// when the direct kernel cannot use whole vectors -- for 4-byte inputs unless
+// m and k are multiples of 4 (then the k-contiguous operand and C load as
+// 16-byte vectors), for 8-byte inputs up to 11 rows/columns (longer f64 rows
+// fill their cache lines directly).  The smaller classes and the complex
+// types (four real products per step double the LDS gathers) stay direct.
+template <typename T, typename TI>
+inline bool staged_rule(const GemmArgs<T>& a)
 {
-    const int path = tuning().path;
-    if (path == 1) return false;
-    if (path == 2) return true;
     const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
-    return !(sizeof(T) >= 8 && mx >= 7);
+    if (Tr<T>::cplx || size_class(a.m, a.n, a.k) != 16) return false;
+    return sizeof(TI) >= 8 ? mx <= 11 : !((a.m & 3) == 0 && (a.k & 3) == 0);
 }
 
-// Strided / pointer-array dispatch: sizes <= 8 through the team kernel (when
-// chosen), packed strided batches through the LDS-staged kernel (when
-// enabled), everything else through the direct one.
+// The built-in rule for the team kernel (measured, N = 100,000, square): it
+// is ahead for every size <= 8 except 8-byte and larger elements at 7 and 8,
+// where the MFMA tiles are full enough to win.
+template <typename T>
+inline bool team_rule(const GemmArgs<T>& a)
+{
+    const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
+    return mx <= 8 && !(sizeof(T) >= 8 && mx >= 7);
+}
+
+template <typename T> struct TypeCode;
+template <> struct TypeCode<float> { static constexpr int v = 0; };
+template <> struct TypeCode<double> { static constexpr int v = 1; };
+template <> struct TypeCode<float2> { static constexpr int v = 2; };
+template <> struct TypeCode<double2> { static constexpr int v = 3; };
+
+enum class Kern { Direct, Staged, Team, Blocked };
+
+// The kernel and launch shape of one call: explicit knobs first, then the
+// tuned table's entry for (type, form, op pair, size), then the built-in
+// rules.  Fills the plan_* fields of a, and G for the staged kernel.
+template <typename T, typename TI, int MODE>
+inline Kern plan_gemm(GemmArgs<T>& a, bool pointer_form)
+{
+    a.plan_wg = a.plan_xcd = a.plan_unroll = 0;
+    a.G = 0;
+    if (a.m > 16 || a.n > 16 || a.k > 16) return Kern::Blocked;
+    const Tuning& tu = tuning();
+    const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
+    const int D = size_class(a.m, a.n, a.k);
+    constexpr bool plain = MODE == 0 && std::is_same<T, TI>::value;
+    const TunedEntry* te = (plain && tu.table) ? tuned_entry(TypeCode<T>::v, pointer_form, a.a_trans, a.b_trans, mx)
+                                               : nullptr;
+    if (te) {
+        if (tu.wg_per_cu == 0) a.plan_wg = te->wg_per_cu;
+        if (tu.xcd_chunk == 0) a.plan_xcd = te->xcd_chunk;
+        a.plan_unroll = te->unroll;
+    }
+    if (tu.unroll > 0) a.plan_unroll = tu.unroll;
+    if (plain) {
+        const bool team_ok = D <= 8 || (D == 16 && !Tr<T>::cplx);
+        bool team;
+        if (tu.path == 1) team = false;
+        else if (tu.path == 2) team = D <= 8;
+        else if (tu.path == 3) team = team_ok;
+        else if (te && te->path) team = te->path == 2;
+        else team = team_rule(a);
+        if (team && team_ok) return Kern::Team;
+    }
+    if (!pointer_form && is_packed(a) && !a.scaleA && tu.staged != 0) {
+        bool st;
+        if (tu.staged == 1) st = true;
+        else if (te && te->path && tu.path == 0) st = te->path == 3;
+        else st = staged_rule<T, TI>(a);
+        if (st) a.G = staged_run_length<T, TI>(a.m, a.n, a.k, a.batch, device_cu_count() * 16);
+        if (a.G > 0) return Kern::Staged;
+    }
+    return Kern::Direct;
+}
+
+// Strided / pointer-array dispatch after plan_gemm: the team kernel, the
+// LDS-staged kernel for packed strided batches, the direct MFMA tile kernel,
+// or the sub-blocked kernel above 16.
 template <typename T, typename TI, int MODE>
 hipError_t launch_direct(GemmArgs<T> a, bool pointer_form, hipStream_t stream)
 {
-    // sizes above 16: the sub-blocked kernel (plain types only)
-    if (a.m > 16 || a.n > 16 || a.k > 16) {
+    const Kern kind = plan_gemm<T, TI, MODE>(a, pointer_form);
+    if (kind == Kern::Blocked) {
         if constexpr (MODE == 0 && std::is_same<T, TI>::value) return launch_blocked<T>(a, pointer_form, stream);
         return hipErrorInvalidValue;
     }
     const int D = size_class(a.m, a.n, a.k);
     if constexpr (MODE == 0 && std::is_same<T, TI>::value)
-        if (D <= 8 && team_choice<T>(a)) return launch_team<T>(a, pointer_form, stream);
-    a.G = staged_choice<T, TI>(a, pointer_form);
-    if (a.G > 0) {
+        if (kind == Kern::Team) return launch_team<T>(a, pointer_form, stream);
+    if (kind == Kern::Staged) {
         if (D == 4) return launch_staged_ops<T, TI, MODE, 4>(a, stream);
         if (D == 8) return launch_staged_ops<T, TI, MODE, 8>(a, stream);
         return launch_staged_ops<T, TI, MODE, 16>(a, stream);
@@ -407,17 +452,16 @@ int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
         return snprintf(buf, len, "void sbg::gemm_blocked_kernel<%s, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
                         TypeName<T>::s, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form), TypeName<T>::s);
     }
+    const Kern kind = plan_gemm<T, T, 0>(a, pointer_form);
     const int D = size_class(a.m, a.n, a.k);
-    if (D <= 8 && team_choice<T>(a)) {
+    if (kind == Kern::Team)
         return snprintf(buf, len, "void sbg::gemm_team_kernel<%s, %d, %s, %s, %s, %s>(sbg::GemmArgs<%s>)",
                         TypeName<T>::s, D, tf(!a.a_trans), tf(!a.b_trans), tf(team_vec(a)), tf(pointer_form),
                         TypeName<T>::s);
-    }
-    const int G = staged_choice<T, T>(a, pointer_form);
-    if (G > 0)
+    if (kind == Kern::Staged)
         return snprintf(buf, len, "void sbg::gemm_staged_kernel<%s, %s, 0, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
                         TypeName<T>::s, TypeName<T>::s, D, tf(a.a_trans), tf(!a.b_trans),
-                        tf(staged_whole_chunks(a.m, a.n, a.k, G, (int)sizeof(T), (int)sizeof(T))), TypeName<T>::s);
+                        tf(staged_whole_chunks(a.m, a.n, a.k, a.G, (int)sizeof(T), (int)sizeof(T))), TypeName<T>::s);
     const int U = D == 4 ? choose_unroll<T, T, 4>(a) : (D == 8 ? choose_unroll<T, T, 8>(a) : choose_unroll<T, T, 16>(a));
     return snprintf(buf, len, "void sbg::gemm_mfma_kernel<%s, %s, 0, %d, %d, %s, %s, %s, %s>(sbg::GemmArgs<%s>)",
                     TypeName<T>::s, TypeName<T>::s, D, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form),

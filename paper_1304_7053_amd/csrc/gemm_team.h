@@ -1,5 +1,5 @@
-// Batched GEMM for matrices whose sizes are all <= 8 (size classes 4 and 8):
-// one team of lanes per matrix, one lane per column.
+// Batched GEMM for small matrices (size classes 4 and 8, and 16 for the real
+// types): one team of lanes per matrix, one lane per column.
 //
 // The operation is memory-bound at these sizes (at most 2 flops per byte), so
 // the design is about moving each matrix's bytes in as few, as wide and as
@@ -284,13 +284,27 @@ __global__ __launch_bounds__(256) void gemm_team_kernel(const GemmArgs<T> a)
             SBG_TEAM_CASE(3)
             SBG_TEAM_CASE(4)
             default:
-                if constexpr (D == 8) {
+                if constexpr (D >= 8) {
                     switch (k) {
                         SBG_TEAM_CASE(5)
                         SBG_TEAM_CASE(6)
                         SBG_TEAM_CASE(7)
                         SBG_TEAM_CASE(8)
-                        default: break;
+                        default:
+                            if constexpr (D == 16) {
+                                switch (k) {
+                                    SBG_TEAM_CASE(9)
+                                    SBG_TEAM_CASE(10)
+                                    SBG_TEAM_CASE(11)
+                                    SBG_TEAM_CASE(12)
+                                    SBG_TEAM_CASE(13)
+                                    SBG_TEAM_CASE(14)
+                                    SBG_TEAM_CASE(15)
+                                    SBG_TEAM_CASE(16)
+                                    default: break;
+                                }
+                            }
+                            break;
                     }
                 }
                 break;
@@ -347,12 +361,18 @@ hipError_t launch_team_ops(const GemmArgs<T>& a, hipStream_t stream)
               : launch_team_modes<T, D, false, false, PTR>(a, stream);
 }
 
-// Entry from the strided / pointer-array dispatch (sizes <= 8, plain types).
+// Entry from the strided / pointer-array dispatch (sizes <= 8, and <= 16 for
+// the real types).
 template <typename T>
 hipError_t launch_team(const GemmArgs<T>& a, bool pointer_form, hipStream_t stream)
 {
     const int D = size_class(a.m, a.n, a.k);
-    if (D > 8) return hipErrorInvalidValue;
+    if (D == 16) {
+        if constexpr (!Tr<T>::cplx) {
+            return pointer_form ? launch_team_ops<T, 16, true>(a, stream) : launch_team_ops<T, 16, false>(a, stream);
+        }
+        return hipErrorInvalidValue;
+    }
     if (pointer_form) return D == 4 ? launch_team_ops<T, 4, true>(a, stream) : launch_team_ops<T, 8, true>(a, stream);
     return D == 4 ? launch_team_ops<T, 4, false>(a, stream) : launch_team_ops<T, 8, false>(a, stream);
 }

@@ -38,6 +38,8 @@ struct GemmArgs {
     int64_t batch;
     int64_t xcd_chunk;             // consecutive work units per XCD run (set by the launcher)
     int64_t blocks;                // work-groups with work in a one-shot grid (set by the launcher)
+    int plan_wg, plan_xcd;         // launch shape chosen for this call (0: the tuning knobs' defaults)
+    int plan_unroll;               // tiles per wave step of the direct kernel (0: from the byte budgets)
     int G;                         // matrices per wave step of the LDS-staged kernel
     // variable-size form: per-matrix sizes and leading dimensions, workspace
     const int* dm;
@@ -50,23 +52,40 @@ struct GemmArgs {
     int* ws;
 };
 
-// Launch-shape knobs: work-groups per CU of the persistent grid, the XCD run
-// length, which packed batches take the LDS-staged kernel and the per-wave
-// byte budgets that choose the direct kernel's tile unroll.  Defaults are the
-// tuned values; SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED, SBG_TILE_BYTES,
-// SBG_TILE_BYTES16 and SBG_PIPELINE override them (read once per process) for
-// tuning sweeps and A/B comparisons.
+// Launch-shape and kernel-choice knobs.  A value of 0 (2 for `staged`) means
+// automatic: the entry of the tuned table for the call when one is loaded,
+// else the built-in rule or default (4 work-groups per CU, XCD runs of 16,
+// tile unroll from the byte budgets).  Non-automatic values, set through
+// sbg_set_tuning or the SBG_* environment variables (read once per process),
+// override the table -- for tuning sweeps and A/B comparisons.
 struct Tuning {
-    int wg_per_cu;
-    int xcd_chunk;
-    int staged;        // 0 never, 1 every packed strided batch, 2 the 16 class except 16x16x16
+    int wg_per_cu;     // persistent grids: work-groups per CU (capped by occupancy)
+    int xcd_chunk;     // consecutive work units per XCD run
+    int staged;        // 0 never, 1 every packed strided batch, 2 automatic
     int tile_bytes;    // per-wave bytes in flight per step, size classes 4 and 8
     int tile_bytes16;  // the same for size class 16, per 4-byte element size (scaled by sizeof(T) / 4)
     bool pipeline;     // issue the next group's loads before computing the current one
-    int path;          // sizes <= 8: 0 automatic, 1 MFMA tile kernels only, 2 team kernel whenever it applies
+    int path;          // 0 automatic, 1 MFMA tile kernels only, 2 team kernel for sizes <= 8, 3 also for the
+                       // real types up to 16
+    int unroll;        // tiles per wave step of the direct kernel (a power of two, capped per class)
+    int grid;          // work-groups of a persistent grid (rounded up to a multiple of 8)
+    int table;         // 1: use the tuned table when one is loaded
 };
 const Tuning& tuning();
 Tuning& tuning_mut();
+
+// One entry of the tuned table (kernel choice and launch shape measured for a
+// type, batch form, op pair and size), read from the versioned JSON file the
+// autotuner writes.  path: 1 MFMA tile kernel, 2 team kernel, 3 LDS-staged
+// kernel; 0 fields mean "no preference".
+struct TunedEntry {
+    int path, unroll, wg_per_cu, xcd_chunk;
+};
+// Entry for type code (0 S, 1 D, 2 C, 3 Z), form (pointer arrays or strided),
+// transposed op(A) / op(B) and size max(m, n, k) in 1..16, or null.
+const TunedEntry* tuned_entry(int type, bool pointer_form, bool a_trans, bool b_trans, int size);
+// "file=... version=... entries=..." into buf; returns the entry count.
+int tuned_table_info(char* buf, int len);
 
 // Compute units of the current device, cached per device.
 int device_cu_count();

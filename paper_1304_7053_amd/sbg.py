@@ -41,7 +41,7 @@ EXPORTS = [
     "sbg_quantize_e4m3_strided_batched", "sbg_quantize_e4m3_vbatched", "sbg_set_tuning", "sbg_get_tuning",
     "sbg_sgemv_strided_batched", "sbg_dgemv_strided_batched", "sbg_cgemv_strided_batched",
     "sbg_zgemv_strided_batched", "sbg_strsm_strided_batched", "sbg_dtrsm_strided_batched",
-    "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched", "sbg_gemm_vbatched_ex_noalloc",
+    "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched", "sbg_gemm_vbatched_ex_noalloc", "sbg_tuned_table_info",
 ]
 
 
@@ -113,6 +113,8 @@ def load():
     lib.sbg_set_tuning.restype = c_int
     lib.sbg_get_tuning.argtypes = [ctypes.c_char_p]
     lib.sbg_get_tuning.restype = c_int
+    lib.sbg_tuned_table_info.argtypes = [ctypes.c_char_p, c_int]
+    lib.sbg_tuned_table_info.restype = c_int
     _lib = lib
     return lib
 
@@ -360,6 +362,13 @@ def get_tuning(key):
     if v < 0:
         raise ValueError(f"unknown tuning key {key}")
     return v
+
+
+def tuned_table_info():
+    """(entry count, description) of the tuned table the library loaded."""
+    buf = ctypes.create_string_buffer(1024)
+    n = load().sbg_tuned_table_info(buf, len(buf))
+    return n, buf.value.decode()
 
 
 class tuned:

@@ -151,30 +151,32 @@ def test_status_strings_and_mode():
 
 
 def test_tuning_knobs_round_trip():
-    """Launch-tuning knobs: defaults, set returns the previous value, invalid
-    keys and out-of-range values are rejected without changing anything."""
+    """Launch-tuning knobs: defaults (0 = automatic: tuned table or built-in
+    rule), set returns the previous value, invalid keys and out-of-range
+    values are rejected without changing anything."""
     lib = sbg.load()
-    defaults = {"wg_per_cu": 4, "xcd_chunk": 16, "staged": 2, "tile_bytes": 2048, "tile_bytes16": 8192,
-                "pipeline": 0}
-    env = {"wg_per_cu": "SBG_WG_PER_CU", "xcd_chunk": "SBG_XCD_CHUNK", "staged": "SBG_STAGED",
-           "tile_bytes": "SBG_TILE_BYTES", "tile_bytes16": "SBG_TILE_BYTES16", "pipeline": "SBG_PIPELINE"}
+    defaults = {"wg_per_cu": 0, "xcd_chunk": 0, "staged": 2, "tile_bytes": 2048, "tile_bytes16": 8192,
+                "pipeline": 0, "path": 0, "unroll": 0, "grid": 0, "table": 1}
     for key, want in defaults.items():
-        if env[key] not in os.environ:
-            assert sbg.get_tuning(key) == want
+        if "SBG_" + key.upper() not in os.environ:
+            assert sbg.get_tuning(key) == want, key
     old = sbg.set_tuning("staged", 1)
     assert sbg.get_tuning("staged") == 1
     assert sbg.set_tuning("staged", old) == 1
-    for key, bad in (("staged", 3), ("staged", -1), ("wg_per_cu", 0), ("wg_per_cu", 33), ("tile_bytes", 255),
-                     ("tile_bytes16", 1 << 21), ("xcd_chunk", 0)):
+    for key, bad in (("staged", 3), ("staged", -1), ("wg_per_cu", -1), ("wg_per_cu", 33), ("tile_bytes", 255),
+                     ("tile_bytes16", 1 << 21), ("xcd_chunk", -1), ("path", 4), ("unroll", 9), ("grid", -1),
+                     ("table", 2)):
         before = sbg.get_tuning(key)
         assert lib.sbg_set_tuning(key.encode(), bad) == -1
         assert sbg.get_tuning(key) == before
     assert lib.sbg_set_tuning(b"no_such_knob", 1) == -1
     assert lib.sbg_get_tuning(b"no_such_knob") == -1
     assert lib.sbg_set_tuning(None, 1) == -1
-    with sbg.tuned(pipeline=1, tile_bytes=4096):
+    with sbg.tuned(pipeline=1, tile_bytes=4096, path=3, unroll=2, grid=512, table=0):
         assert sbg.get_tuning("pipeline") == 1 and sbg.get_tuning("tile_bytes") == 4096
+        assert (sbg.get_tuning("path"), sbg.get_tuning("unroll"), sbg.get_tuning("grid")) == (3, 2, 512)
     assert sbg.get_tuning("tile_bytes") == defaults["tile_bytes"] or "SBG_TILE_BYTES" in os.environ
+    assert sbg.get_tuning("table") == 1 or "SBG_TABLE" in os.environ
 
 
 def test_vbatched_workspace_validation():
