@@ -1,5 +1,6 @@
 // Mixed-precision kernel instances: A and B stored as bf16_t, mode 0 (see gemm_ex.hip).
 #include "gemm_vbatched.h"
+#include "gemm_vbteam.h"
 #include "gemm_staged.h"
 
 namespace sbg {

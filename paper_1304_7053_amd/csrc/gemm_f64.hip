@@ -1,5 +1,6 @@
 // Kernel instances for element type double (all size classes, both batch forms).
 #include "gemm_vbatched.h"
+#include "gemm_vbteam.h"
 #include "gemm_staged.h"
 #include "gemm_blocked.h"
 #include "gemm_team.h"

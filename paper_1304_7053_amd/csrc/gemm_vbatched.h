@@ -29,7 +29,8 @@
 namespace sbg {
 
 constexpr int VB_HEADER_BYTES = 64;
-constexpr int VB_BIN_PER = 4;   // matrices per thread of the binning kernel
+constexpr int VB_BIN_PER = 2;        // matrices per thread of the binning kernel
+constexpr int VB_BIN_THREADS = 1024;  // threads per work-group of the binning kernel
 
 // One binned matrix.
 struct alignas(16) VbRec {
@@ -55,7 +56,7 @@ __device__ __host__ inline const VbRec* vb_list(const int* ws, int64_t batch, in
 }
 
 __global__ void vb_zero_kernel(int* ws);
-__global__ __launch_bounds__(256) void vb_bin_kernel(const int* dm, const int* dn, const int* dk, const int* dlda,
+__global__ __launch_bounds__(VB_BIN_THREADS) void vb_bin_kernel(const int* dm, const int* dn, const int* dk, const int* dlda,
                                                      const int* dldb, const int* dldc, const void* const* Aarr,
                                                      const void* const* Barr, void* const* Carr,
                                                      const float* scaleA, const float* scaleB, int max_m,
@@ -127,8 +128,8 @@ template <typename T, typename TI, int MODE, bool ACONT, bool BCONT>
 hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
 {
     hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
-    const int64_t nb = (a.batch + 256 * VB_BIN_PER - 1) / (256 * VB_BIN_PER);
-    hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(256), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,
+    const int64_t nb = (a.batch + VB_BIN_THREADS * VB_BIN_PER - 1) / (VB_BIN_THREADS * VB_BIN_PER);
+    hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(VB_BIN_THREADS), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,
                        a.dldc, a.Aarr, a.Barr, reinterpret_cast<void* const*>(a.Carr), a.scaleA, a.scaleB,
                        a.max_m, a.max_n, a.max_k, a.a_trans, a.b_trans, a.batch, a.ws);
     auto kern = gemm_vbatched_kernel<T, TI, MODE, ACONT, BCONT>;
@@ -140,9 +141,16 @@ hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
     return hipGetLastError();
 }
 
+template <typename T, typename TI>
+hipError_t launch_vbteam(const GemmArgs<T>& a, hipStream_t stream);
+
 template <typename T, typename TI, int MODE>
 hipError_t launch_vbatched_t(const GemmArgs<T>& a, hipStream_t stream)
 {
+    // real types in plain mode: one team of lanes per matrix (gemm_vbteam.h);
+    // complex types, BF16x3 and the `path` knob set to 1: the MFMA tiles
+    if constexpr (MODE == 0 && !Tr<T>::cplx)
+        if (tuning().path != 1) return launch_vbteam<T, TI>(a, stream);
     const bool at = a.a_trans, bn = !a.b_trans;
     if (at) {
         if (bn) return launch_vb_variant<T, TI, MODE, true, true>(a, stream);

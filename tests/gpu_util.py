@@ -70,6 +70,12 @@ class Case:
         torch.cuda.synchronize()
         return from_dev(dC)
 
+    def describe(self):
+        """Name of the kernel the library picks for this case's strided call."""
+        prefix = {np.float32: "s", np.float64: "d", np.complex64: "c", np.complex128: "z"}[np.dtype(self.dtype).type]
+        return sbg.describe_strided(prefix, self.ta, self.tb, self.m, self.n, self.k,
+                                    self.lda, self.sA, self.ldb, self.sB, self.ldc, self.sC, self.batch)
+
     def unpack(self, flat, idx=None):
         """(len(idx), m, n) view of matrices idx of a flat C-layout array."""
         idx = np.arange(self.batch) if idx is None else np.asarray(idx)

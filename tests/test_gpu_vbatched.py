@@ -36,11 +36,36 @@ def test_vbatched_mixed_sizes_all_ops(gpu_lib, dtype):
             check_var(c, out, label="vbatched")
             ws = from_dev(d["ws"])
             assert ws[3] == 0
-            assert ws[0] + ws[1] + ws[2] == c.batch
+            if np.dtype(dtype).kind == "c":
+                # the MFMA path bins the batch: the class counts cover it
+                assert ws[0] + ws[1] + ws[2] == c.batch
             inside = np.zeros(c.C.shape, dtype=bool)
             for p in range(c.batch):
                 inside[c.offC[p] + np.arange(c.m[p])[:, None] + np.arange(c.n[p])[None, :] * c.ldc[p]] = True
             assert np.array_equal(out[~inside].view(np.uint8), c.C[~inside].view(np.uint8))
+
+
+@pytest.mark.parametrize("bound", [4, 8], ids=lambda b: f"max{b}")
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=lambda d: np.dtype(d).name)
+def test_vbatched_team_size_from_bounds(gpu_lib, dtype, bound):
+    """Real types run with teams of the size class of the declared bounds:
+    sizes 0..bound drawn independently (NaN between the matrices), every op
+    pair against the oracle; a matrix above the bounds is skipped and counted."""
+    g = inputs.rng(4, salt=10 + bound)
+    al, be = scalars(dtype)
+    N = 517
+    for ta in "NT":
+        for tb in "NT":
+            m, n, k = (g.integers(0, bound + 1, size=N).astype(np.int32) for _ in range(3))
+            m[7], n[7], k[7] = bound, bound, bound
+            m[8] = bound + 1                   # above max_m: rejected
+            c = VarCase(dtype, ta, tb, (m, n, k), al, be, g)
+            say(f"vbatched team bound={bound} {np.dtype(dtype).name} {ta}{tb}")
+            out, d = c.run_gpu(maxes=(bound, bound, bound))
+            ws = from_dev(d["ws"])
+            assert ws[3] == 1
+            assert np.array_equal(c.got(out, 8).view(np.uint8), c.got(c.C, 8).view(np.uint8))
+            check_var(c, out, idx=np.array([p for p in range(N) if p != 8]), label=f"bound {bound}")
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.complex128], ids=lambda d: np.dtype(d).name)
@@ -86,31 +111,49 @@ def test_vbatched_rejects_invalid_matrices(gpu_lib):
     check_var(c, out, idx=good, label="valid part")
 
 
-@pytest.mark.parametrize("dtype", [np.float32, np.complex64], ids=lambda d: np.dtype(d).name)
+def _vbatched_uniform(cs, dtype, al, be):
+    """The strided case `cs` (one size) run through the variable-size entry
+    point; returns the resulting C."""
+    s, N = cs.m, cs.batch
+    esz = np.dtype(dtype).itemsize
+    dA, dB, dC = to_dev(cs.A), to_dev(cs.B), to_dev(cs.C)
+    p = np.arange(N)
+    full = lambda v: torch.full((N,), v, dtype=torch.int32, device="cuda")  # noqa: E731
+    ws = torch.zeros(sbg.vbatched_workspace_size(N) // 4 + 1, dtype=torch.int32, device="cuda")
+    sbg.gemm_vbatched(cs.ta, cs.tb, full(s), full(s), full(s), s, s, s, al,
+                      torch.tensor(dA.data_ptr() + p * cs.sA * esz, device="cuda"), full(cs.lda),
+                      torch.tensor(dB.data_ptr() + p * cs.sB * esz, device="cuda"), full(cs.ldb), be,
+                      torch.tensor(dC.data_ptr() + p * cs.sC * esz, device="cuda"), full(cs.ldc), N, ws,
+                      dC.dtype)
+    torch.cuda.synchronize()
+    return from_dev(dC)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.complex64], ids=lambda d: np.dtype(d).name)
 def test_vbatched_matches_strided_bitwise(gpu_lib, dtype):
-    """With every matrix of one size the variable-size kernel runs the same
-    per-matrix arithmetic as the strided MFMA tile kernel: results agree bit
-    for bit."""
+    """With every matrix of one size the variable-size kernels run the same
+    per-matrix arithmetic as the strided ones: the MFMA variable-size kernel
+    (path 1) equals the strided MFMA tile kernel, and the team variable-size
+    kernel (the default for real types) equals the strided team kernel, bit
+    for bit, for every op pair."""
     g = inputs.rng(4, salt=4)
     al, be = scalars(dtype)
-    for s in (3, 8, 13, 16):
-        cs = Case(dtype, "T", "N", s, s, s, 257, al, be, g)
-        with sbg.tuned(path=1):
-            ref = cs.run_gpu()
-        N = cs.batch
-        esz = np.dtype(dtype).itemsize
-        dA, dB, dC = to_dev(cs.A), to_dev(cs.B), to_dev(cs.C)
-        p = np.arange(N)
-        full = lambda v: torch.full((N,), v, dtype=torch.int32, device="cuda")  # noqa: E731
-        ws = torch.zeros(sbg.vbatched_workspace_size(N) // 4 + 1, dtype=torch.int32, device="cuda")
-        say(f"vbatched == strided {np.dtype(dtype).name} n={s}")
-        sbg.gemm_vbatched("T", "N", full(s), full(s), full(s), s, s, s, al,
-                          torch.tensor(dA.data_ptr() + p * cs.sA * esz, device="cuda"), full(cs.lda),
-                          torch.tensor(dB.data_ptr() + p * cs.sB * esz, device="cuda"), full(cs.ldb), be,
-                          torch.tensor(dC.data_ptr() + p * cs.sC * esz, device="cuda"), full(cs.ldc), N, ws,
-                          dC.dtype)
-        torch.cuda.synchronize()
-        assert np.array_equal(from_dev(dC).view(np.uint8), ref.view(np.uint8))
+    real = np.dtype(dtype).kind == "f"
+    for ta, tb in (("T", "N"), ("N", "N"), ("N", "T"), ("T", "T")):
+        for s in (3, 8, 13, 16):
+            cs = Case(dtype, ta, tb, s, s, s, 257, al, be, g)
+            say(f"vbatched == strided {np.dtype(dtype).name} {ta}{tb} n={s} (MFMA)")
+            with sbg.tuned(path=1):
+                ref = cs.run_gpu()
+                got = _vbatched_uniform(cs, dtype, al, be)
+            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+            if real:
+                say(f"vbatched == strided {np.dtype(dtype).name} {ta}{tb} n={s} (team)")
+                with sbg.tuned(path=3):
+                    assert "gemm_team_kernel" in cs.describe()
+                    ref = cs.run_gpu()
+                got = _vbatched_uniform(cs, dtype, al, be)
+                assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=lambda d: np.dtype(d).name)
