@@ -361,6 +361,20 @@ int sbg_tuned_table_info(char* buf, int buflen);
 int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, int k, int lda,
                          int64_t strideA, int ldb, int64_t strideB, int ldc, int64_t strideC,
                          int64_t batch_count, char* buf, int buflen);
+/* sbg_describe_vbatched: the same for a variable-size call (prefix 's' goes
+ *   through sbg_gemm_vbatched_ex with ab_type and mode; 'd', 'c', 'z' through
+ *   the typed entry points and need SBG_R_32F / SBG_MODE_PLAIN).  Writes
+ *   "kernel=<symbol> grid=<work-groups> units=<work units>": the persistent
+ *   kernel, the work-groups the launcher would start (each runs 4 waves) and
+ *   its work units (wave steps; for the binned MFMA path the upper bound,
+ *   every matrix in the 16 class, followed by "u16= u8= u4=", the matrices
+ *   per lane group and wave step of each class).  Launches nothing, touches
+ *   no device memory (the grid comes from an occupancy query of the current
+ *   device).  Returns 0, or -1 when the call would be rejected or return
+ *   early. */
+int sbg_describe_vbatched(char prefix, char transa, char transb, int max_m, int max_n, int max_k,
+                          int64_t batch_count, sbg_datatype_t ab_type, sbg_compute_mode_t mode, char* buf,
+                          int buflen);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,12 @@ Tuning& tuning_mut()
 
 const Tuning& tuning() { return tuning_mut(); }
 
+VbDescribe& vb_describe()
+{
+    thread_local VbDescribe d;
+    return d;
+}
+
 namespace {
 
 enum Op { OP_N, OP_T, OP_C, OP_R, OP_BAD };
@@ -942,6 +948,60 @@ int sbg_describe_strided(char prefix, char transa, char transb, int m, int n, in
     }
     sbg::tl_describe_buf = nullptr;
     sbg::tl_describe_len = 0;
+    return st == SBG_OK && buf[0] ? 0 : -1;
+}
+
+int sbg_describe_vbatched(char prefix, char transa, char transb, int max_m, int max_n, int max_k,
+                          int64_t batch_count, sbg_datatype_t ab_type, sbg_compute_mode_t mode, char* buf,
+                          int buflen)
+{
+    if (!buf || buflen <= 0) return -1;
+    buf[0] = 0;
+    if (prefix != 's' && (ab_type != SBG_R_32F || mode != SBG_MODE_PLAIN)) return -1;
+    // fake, never dereferenced device addresses (16-byte aligned): the
+    // describe path returns before any launch
+    void* fake = reinterpret_cast<void*>(static_cast<uintptr_t>(256));
+    const int* di = static_cast<const int*>(fake);
+    const double one[2] = {1.5, 0.0}, half[2] = {0.5, 0.0};
+    const float onef[2] = {1.5f, 0.f}, halff[2] = {0.5f, 0.f};
+    const size_t big = ~size_t(0);
+    sbg::VbDescribe& ds = sbg::vb_describe();
+    ds.buf = buf;
+    ds.len = buflen;
+    sbg_status_t st = SBG_INVALID_VALUE;
+    switch (prefix) {
+    case 's':
+        st = sbg_gemm_vbatched_ex(transa, transb, di, di, di, max_m, max_n, max_k, onef,
+                                  static_cast<const void* const*>(fake), di, static_cast<const float*>(fake),
+                                  static_cast<const void* const*>(fake), di, static_cast<const float*>(fake), halff,
+                                  static_cast<float* const*>(fake), di, batch_count, ab_type, mode, fake, big,
+                                  nullptr);
+        break;
+    case 'd':
+        st = sbg_dgemm_vbatched(transa, transb, di, di, di, max_m, max_n, max_k, one,
+                                static_cast<const double* const*>(fake), di, static_cast<const double* const*>(fake),
+                                di, half, static_cast<double* const*>(fake), di, batch_count, fake, big, nullptr);
+        break;
+    case 'c':
+        st = sbg_cgemm_vbatched(transa, transb, di, di, di, max_m, max_n, max_k,
+                                reinterpret_cast<const sbg_cfloat*>(onef),
+                                static_cast<const sbg_cfloat* const*>(fake), di,
+                                static_cast<const sbg_cfloat* const*>(fake), di,
+                                reinterpret_cast<const sbg_cfloat*>(halff), static_cast<sbg_cfloat* const*>(fake), di,
+                                batch_count, fake, big, nullptr);
+        break;
+    case 'z':
+        st = sbg_zgemm_vbatched(transa, transb, di, di, di, max_m, max_n, max_k,
+                                reinterpret_cast<const sbg_cdouble*>(one),
+                                static_cast<const sbg_cdouble* const*>(fake), di,
+                                static_cast<const sbg_cdouble* const*>(fake), di,
+                                reinterpret_cast<const sbg_cdouble*>(half), static_cast<sbg_cdouble* const*>(fake),
+                                di, batch_count, fake, big, nullptr);
+        break;
+    default: break;
+    }
+    ds.buf = nullptr;
+    ds.len = 0;
     return st == SBG_OK && buf[0] ? 0 : -1;
 }
 

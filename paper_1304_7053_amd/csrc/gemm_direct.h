@@ -439,6 +439,9 @@ template <> struct TypeName<float> { static constexpr const char* s = "float"; }
 template <> struct TypeName<double> { static constexpr const char* s = "double"; };
 template <> struct TypeName<float2> { static constexpr const char* s = "HIP_vector_type<float, 2u>"; };
 template <> struct TypeName<double2> { static constexpr const char* s = "HIP_vector_type<double, 2u>"; };
+template <> struct TypeName<bf16_t> { static constexpr const char* s = "sbg::bf16_t"; };
+template <> struct TypeName<f16_t> { static constexpr const char* s = "sbg::f16_t"; };
+template <> struct TypeName<e4m3_t> { static constexpr const char* s = "sbg::e4m3_t"; };
 
 // The kernel symbol (as profilers demangle it) a plain launch with these
 // arguments uses, written into buf.

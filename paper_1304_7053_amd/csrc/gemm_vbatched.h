@@ -127,6 +127,20 @@ __global__ __launch_bounds__(256) void gemm_vbatched_kernel(const GemmArgs<T> a)
 template <typename T, typename TI, int MODE, bool ACONT, bool BCONT>
 hipError_t launch_vb_variant(GemmArgs<T> a, hipStream_t stream)
 {
+    if (VbDescribe& ds = vb_describe(); ds.buf) {
+        // the class counts are only known on the device: units is the upper
+        // bound (every matrix in the 16 class); the lists are walked 16, 8, 4
+        const auto tf = [](bool b) { return b ? "true" : "false"; };
+        auto kern = gemm_vbatched_kernel<T, TI, MODE, ACONT, BCONT>;
+        const int64_t units = (a.batch + Unroll<T, 16>::value - 1) / Unroll<T, 16>::value;
+        const int64_t grid = persistent_grid(kern, units, a);
+        snprintf(ds.buf, ds.len,
+                 "kernel=void sbg::gemm_vbatched_kernel<%s, %s, %d, %s, %s>(sbg::GemmArgs<%s>) grid=%lld units=%lld "
+                 "u16=%d u8=%d u4=%d",
+                 TypeName<T>::s, TypeName<TI>::s, MODE, tf(ACONT), tf(BCONT), TypeName<T>::s, (long long)grid,
+                 (long long)units, Unroll<T, 16>::value, Unroll<T, 8>::value, Unroll<T, 4>::value);
+        return hipSuccess;
+    }
     hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
     const int64_t nb = (a.batch + VB_BIN_THREADS * VB_BIN_PER - 1) / (VB_BIN_THREADS * VB_BIN_PER);
     hipLaunchKernelGGL(vb_bin_kernel, dim3((unsigned)nb), dim3(VB_BIN_THREADS), 0, stream, a.dm, a.dn, a.dk, a.dlda, a.dldb,

@@ -16,8 +16,8 @@
 //    chunk(s) holding it -- an aligned chunk never crosses a page, so a load
 //    is never a fault even at the end of an allocation, and bytes outside
 //    the column are dropped.  The partial 16 bytes are re-aligned in
-//    registers (4- and 8-byte types: a select over dwords) or through a
-//    per-lane LDS area (2- and 1-byte types: unaligned 16-byte LDS reads).
+//    registers: selects over dwords, then (2- and 1-byte types) a byte
+//    funnel shift.
 //  * Every load is issued before the first wait (branch-free addresses; an
 //    empty asm makes the loaded registers live before any branch).
 //  * op(A)'s entries reach the team's lanes by DPP broadcasts (no LDS): for
@@ -27,8 +27,8 @@
 //  * C is stored as whole 16-byte vectors plus the vector ending at the
 //    column's end (built in LDS), or element by element for columns shorter
 //    than 16 bytes.
-// Narrow inputs (bf16, fp16, fp8-e4m3 with the matrix's scale product) are
-// decoded to binary32 after loading; products of decoded values are exact in
+// Narrow inputs (bf16, fp16, fp8-e4m3 with the matrix's scale product; e4m3
+// by the hardware conversion) are decoded to binary32 after loading; products of decoded values are exact in
 // binary32, so the result differs from binary32 inputs only by their rounding.
 #pragma once
 
@@ -96,51 +96,39 @@ __device__ __forceinline__ unsigned sel4(const unsigned (&x)[8], int j, int sh)
     return sh == 0 ? a : (sh == 1 ? b : (sh == 2 ? c : d));
 }
 
-// Column bytes 0 .. 16 NV - 1 (past L: garbage) from the raw registers, for
-// 4-byte aligned columns (element size 4 or 8): the partial slot is the last
-// vector (long column) or the aligned chunk (short one) shifted by whole
-// dwords.
-template <int NV>
-__device__ __forceinline__ void vb_fix_dw(vb_u4 (&out)[NV], const VbCol<NV>& r, GBy col, int L)
+// Column bytes 0 .. 16 NV - 1 (past L: garbage) from the raw registers: the
+// partial slot is the last vector (long column) or the aligned chunk (short
+// one) shifted down by a byte count -- whole dwords by selects, the rest
+// (2- and 1-byte elements only, BYTES) by a byte funnel shift.
+template <int NV, bool BYTES>
+__device__ __forceinline__ void vb_fix(vb_u4 (&out)[NV], const VbCol<NV>& r, GBy col, int L)
 {
     const bool lng = L >= 16;
     const int nfull = L >> 4;
-    int sh;
-    if (lng) sh = (16 * nfull - (L - 16)) >> 2;   // in 0..4 (4: no partial slot)
-    else sh = (int)(reinterpret_cast<uintptr_t>(col) & 15) >> 2;
-    sh &= 3;
+    int shb = lng ? 16 * nfull - (L - 16) : (int)(reinterpret_cast<uintptr_t>(col) & 15);
+    shb &= 15;   // 16 (a long column without a partial slot): none
+    const int sh = shb >> 2;
     const vb_u4& t1 = r.next();
     const unsigned x[8] = {r.t0.x, r.t0.y, r.t0.z, r.t0.w, t1.x, t1.y, t1.z, t1.w};
+    unsigned q[4];
+    if constexpr (BYTES) {
+        unsigned y[5];
+#pragma unroll
+        for (int w = 0; w < 5; ++w) y[w] = sel4(x, w, sh);
+        const unsigned sb = (unsigned)shb & 3u;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) q[w] = __builtin_amdgcn_alignbyte(y[w + 1], y[w], sb);
+    } else {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) q[w] = sel4(x, w, sh);
+    }
     vb_u4 p;
-    p.x = sel4(x, 0, sh);
-    p.y = sel4(x, 1, sh);
-    p.z = sel4(x, 2, sh);
-    p.w = sel4(x, 3, sh);
+    p.x = q[0];
+    p.y = q[1];
+    p.z = q[2];
+    p.w = q[3];
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v] = (lng && v < nfull) ? r.s[v] : p;
-}
-
-// The same through a per-lane LDS area of 16 (NV + 2) bytes (any
-// alignment): the slots, then the last vector / chunks, are written at their
-// column offsets (the later writes fix the earlier duplicates), and the
-// column is read back as aligned slots.
-template <int NV>
-__device__ __forceinline__ void vb_fix_lds(vb_u4 (&out)[NV], const VbCol<NV>& r, GBy col, int L, LBy area)
-{
-    const bool lng = L >= 16;
-    const int bs = (int)(reinterpret_cast<uintptr_t>(col) & 15);
-    using LU = __attribute__((address_space(3))) vb_u4u*;
-    using LA = __attribute__((address_space(3))) vb_u4*;
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        *reinterpret_cast<LU>(area + (lng ? 16 + 16 * v : (NV >= 2 && v == 1 ? 32 : 16) - bs)) = r.s[v];
-    if constexpr (NV == 1) *reinterpret_cast<LU>(area + (lng ? 16 : 32 - bs)) = r.t1;
-    *reinterpret_cast<LU>(area + (lng ? L : 16 - bs)) = r.t0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int v = 0; v < NV; ++v) out[v] = *reinterpret_cast<LA>(area + 16 + 16 * v);
 }
 
 // Element e of a column held as 16-byte slots, decoded to the compute type.
@@ -166,9 +154,12 @@ __device__ __forceinline__ T vb_elem(const vb_u4 (&c)[NV], int e)
         x.v = (unsigned short)(w[e >> 1] >> (16 * (e & 1)));
         return (T)dec(x);
     } else {
-        TI x;
-        x.v = (unsigned char)(w[e >> 2] >> (8 * (e & 3)));
-        return (T)dec(x);
+        // OCP E4M3 -> binary32 by the hardware conversion (exact; the
+        // E4M3 NaN codes give NaN), two bytes of a dword per instruction
+        const int word = (int)w[e >> 2];
+        const auto f2 = (e & 2) ? __builtin_amdgcn_cvt_pk_f32_fp8(word, true)
+                                : __builtin_amdgcn_cvt_pk_f32_fp8(word, false);
+        return (T)f2[e & 1];
     }
 }
 
@@ -298,11 +289,21 @@ __device__ __forceinline__ void vbt_dpp_k(T (&acc)[D], const T (&ca)[D], const T
     (vbt_dpp_l<T, D, AC, L>(acc, ca, bv[L], std::make_integer_sequence<int, D>{}), ...);
 }
 
-// The matrix a team serves, read from the caller's arrays: sizes, leading
-// dimensions, pointers and the scale product.  Every load is issued before
-// any is used; a team past the batch re-reads the last matrix (and is
-// invalid), and a null pointer or scale array is read at a valid address with
-// the value replaced.
+// The matrix a team serves, read from the caller's arrays in two stages so
+// that the reads of the next step overlap the current one: vbt_load issues
+// the reads of the sizes, leading dimensions, pointers and scales (a team
+// past the batch re-reads the last matrix; a null pointer or scale array is
+// read at a valid address and the value replaced later), vbt_check turns
+// them into the matrix (checks, rejection).
+struct VbtRaw {
+    const void* A;
+    const void* B;
+    const void* C;
+    int m, n, k, lda, ldb, ldc;
+    float sa, sb;
+    bool in;
+};
+
 struct VbtMat {
     const void* A;
     const void* B;
@@ -314,31 +315,45 @@ struct VbtMat {
 };
 
 template <typename T>
-__device__ __forceinline__ VbtMat vbt_fetch(const GemmArgs<T>& a, int64_t p)
+__device__ __forceinline__ VbtRaw vbt_load(const GemmArgs<T>& a, int64_t p)
 {
-    const bool in = p < a.batch;
-    const int64_t q = in ? p : a.batch - 1;
+    VbtRaw r;
+    r.in = p < a.batch;
+    const int64_t q = r.in ? p : a.batch - 1;
     const void* const* carr = reinterpret_cast<const void* const*>(a.Carr);
-    VbtMat r;
     r.m = a.dm[q];
     r.n = a.dn[q];
     r.k = a.dk[q];
     r.lda = a.dlda[q];
     r.ldb = a.dldb[q];
     r.ldc = a.dldc[q];
-    const void* A = *(a.Aarr ? a.Aarr + q : carr + q);
-    const void* B = *(a.Barr ? a.Barr + q : carr + q);
-    r.C = const_cast<void*>(carr[q]);
-    const float sa = *(a.scaleA ? a.scaleA + q : reinterpret_cast<const float*>(a.dm + q));
-    const float sb = *(a.scaleB ? a.scaleB + q : reinterpret_cast<const float*>(a.dm + q));
-    r.A = a.Aarr ? A : nullptr;
-    r.B = a.Barr ? B : nullptr;
-    r.scale = a.scaleA ? sa * sb : 1.0f;
+    r.A = *(a.Aarr ? a.Aarr + q : carr + q);
+    r.B = *(a.Barr ? a.Barr + q : carr + q);
+    r.C = carr[q];
+    r.sa = *(a.scaleA ? a.scaleA + q : reinterpret_cast<const float*>(a.dm + q));
+    r.sb = *(a.scaleB ? a.scaleB + q : reinterpret_cast<const float*>(a.dm + q));
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ VbtMat vbt_check(const GemmArgs<T>& a, const VbtRaw& w)
+{
+    VbtMat r;
+    r.m = w.m;
+    r.n = w.n;
+    r.k = w.k;
+    r.lda = w.lda;
+    r.ldb = w.ldb;
+    r.ldc = w.ldc;
+    r.A = a.Aarr ? w.A : nullptr;
+    r.B = a.Barr ? w.B : nullptr;
+    r.C = const_cast<void*>(w.C);
+    r.scale = a.scaleA ? w.sa * w.sb : 1.0f;
     const int rowsA = a.a_trans ? r.k : r.m;
     const int rowsB = a.b_trans ? r.n : r.k;
-    r.bad = in && (r.m < 0 || r.n < 0 || r.k < 0 || r.m > a.max_m || r.n > a.max_n || r.k > a.max_k ||
-                   r.lda < (rowsA > 1 ? rowsA : 1) || r.ldb < (rowsB > 1 ? rowsB : 1) || r.ldc < (r.m > 1 ? r.m : 1));
-    r.valid = in && !r.bad && r.m > 0 && r.n > 0;
+    r.bad = w.in && (r.m < 0 || r.n < 0 || r.k < 0 || r.m > a.max_m || r.n > a.max_n || r.k > a.max_k ||
+                     r.lda < (rowsA > 1 ? rowsA : 1) || r.ldb < (rowsB > 1 ? rowsB : 1) || r.ldc < (r.m > 1 ? r.m : 1));
+    r.valid = w.in && !r.bad && r.m > 0 && r.n > 0;
     if (!r.valid) r.m = r.n = r.k = 0;
     return r;
 }
@@ -348,7 +363,7 @@ __device__ __forceinline__ VbtMat vbt_fetch(const GemmArgs<T>& a, int64_t p)
 // columns are operand rows).
 template <typename T, typename TI, int D, bool AC, bool BC>
 __device__ __forceinline__ void vbt_step(const VbtMat& rec, const T& alpha, const T& beta, bool a0, bool b0,
-                                         unsigned char* lds_wave, unsigned char* lane_area)
+                                         unsigned char* lds_wave)
 {
     constexpr int ESI = (int)sizeof(TI);
     constexpr int ESC = (int)sizeof(T);
@@ -392,15 +407,9 @@ __device__ __forceinline__ void vbt_step(const VbtMat& rec, const T& alpha, cons
         if constexpr (NVC == 1) __asm__ volatile("" ::"v"(rc.t1));
     }
 
-    LBy larea = lby(lane_area);
     vb_u4 xa[NVI], xb[NVI];
-    if constexpr (ESI >= 4) {
-        vb_fix_dw<NVI>(xa, ra, cA, LA_);
-        vb_fix_dw<NVI>(xb, rb, cB, LB_);
-    } else {
-        vb_fix_lds<NVI>(xa, ra, cA, LA_, larea);
-        vb_fix_lds<NVI>(xb, rb, cB, LB_, larea + 0);
-    }
+    vb_fix<NVI, (ESI < 4)>(xa, ra, cA, LA_);
+    vb_fix<NVI, (ESI < 4)>(xb, rb, cB, LB_);
     // decoded columns, zero past their length and for columns past the matrix
     const bool okA = valid && has_a && t < na;
     const bool okB = valid && has_a && t < nb;
@@ -415,7 +424,7 @@ __device__ __forceinline__ void vbt_step(const VbtMat& rec, const T& alpha, cons
     // C column (when beta != 0) re-aligned before the compute, so that its
     // raw registers are free during it
     vb_u4 xc[NVC];
-    if (!b0) vb_fix_dw<NVC>(xc, rc, cC, LC_);
+    if (!b0) vb_fix<NVC, false>(xc, rc, cC, LC_);
     T acc[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) acc[i] = T(0);
@@ -517,15 +526,10 @@ __device__ __forceinline__ void vbt_step(const VbtMat& rec, const T& alpha, cons
 }
 
 // Bytes of LDS per wave: the C tail vectors and, for T / C op(B), its rows
-// (D elements of T per lane each), plus, for narrow inputs, a re-alignment
-// area per lane of an odd number of 16-byte units (the lanes' 16-byte
-// accesses fall into different LDS banks).
-template <typename T, typename TI, int D, bool BC>
+// (D elements of T per lane each).
+template <typename T, int D, bool BC>
 struct VbtLds {
-    static constexpr int NVI = (D * (int)sizeof(TI) + 15) / 16;
-    static constexpr int AREA = sizeof(TI) < 4 ? 16 * ((NVI + 2) | 1) : 0;
-    static constexpr int slots = 64 * D * (int)sizeof(T) * (BC ? 1 : 2);
-    static constexpr int bytes = slots + 64 * AREA;
+    static constexpr int bytes = 64 * D * (int)sizeof(T) * (BC ? 1 : 2);
 };
 
 // Persistent kernel over the batch in its own order: wave step grp serves
@@ -535,22 +539,33 @@ template <typename T, typename TI, int D, bool AC, bool BC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1)))
 void gemm_vbteam_kernel(const GemmArgs<T> a)
 {
-    using L = VbtLds<T, TI, D, BC>;
+    using L = VbtLds<T, D, BC>;
     constexpr int TPW = 64 / D;
     __shared__ __attribute__((aligned(16))) unsigned char lds[4 * L::bytes];
     unsigned char* lw = lds + (threadIdx.x >> 6) * L::bytes;
     const int lane = threadIdx.x & 63;
-    unsigned char* area = lw + L::slots + lane * L::AREA;
     T alpha, beta;
     load_scalars(a, alpha, beta);
     const bool a0 = is_zero(alpha), b0 = is_zero(beta);
     const int64_t groups = (a.batch + TPW - 1) / TPW;
     const int64_t W = (int64_t)gridDim.x * 4;
     int nbad = 0;
-    for (int64_t grp = xcd_wave_index(a.xcd_chunk); grp < groups; grp += W) {
-        const VbtMat mt = vbt_fetch(a, grp * TPW + lane / D);
-        nbad += (mt.bad && lane % D == 0) ? 1 : 0;   // counted once per team
-        vbt_step<T, TI, D, AC, BC>(mt, alpha, beta, a0, b0, lw, area);
+    int64_t grp = xcd_wave_index(a.xcd_chunk);
+    if (grp < groups) {
+        VbtRaw raw = vbt_load(a, grp * TPW + lane / D);
+        // the first reads complete before the loop, so that at its head the
+        // wait covers only the reads issued one step earlier
+        __asm__ volatile("" ::"v"(raw.m), "v"(raw.n), "v"(raw.k), "v"(raw.lda), "v"(raw.ldb), "v"(raw.ldc));
+        __asm__ volatile("" ::"v"(raw.A), "v"(raw.B), "v"(raw.C), "v"(raw.sa), "v"(raw.sb));
+        for (; grp < groups; grp += W) {
+            const VbtMat mt = vbt_check(a, raw);
+            // the next step's matrix is read while this one runs (the last
+            // step re-reads its own: the address stays branch-free)
+            const int64_t nx = grp + W < groups ? grp + W : grp;
+            raw = vbt_load(a, nx * TPW + lane / D);
+            nbad += (mt.bad && lane % D == 0) ? 1 : 0;   // counted once per team
+            vbt_step<T, TI, D, AC, BC>(mt, alpha, beta, a0, b0, lw);
+        }
     }
     if (nbad) atomicAdd(&a.ws[3], nbad);
 }
@@ -558,11 +573,19 @@ void gemm_vbteam_kernel(const GemmArgs<T> a)
 template <typename T, typename TI, int D, bool AC, bool BC>
 hipError_t launch_vbteam_variant(GemmArgs<T> a, hipStream_t stream)
 {
-    // the header (word 3: rejected matrices) starts at zero
-    hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
     auto kern = gemm_vbteam_kernel<T, TI, D, AC, BC>;
     const int64_t steps = (a.batch + 64 / D - 1) / (64 / D);
     const int64_t grid = persistent_grid(kern, steps, a);
+    if (VbDescribe& ds = vb_describe(); ds.buf) {
+        const auto tf = [](bool b) { return b ? "true" : "false"; };
+        snprintf(ds.buf, ds.len,
+                 "kernel=void sbg::gemm_vbteam_kernel<%s, %s, %d, %s, %s>(sbg::GemmArgs<%s>) grid=%lld units=%lld",
+                 TypeName<T>::s, TypeName<TI>::s, D, tf(AC), tf(BC), TypeName<T>::s, (long long)grid,
+                 (long long)steps);
+        return hipSuccess;
+    }
+    // the header (word 3: rejected matrices) starts at zero
+    hipLaunchKernelGGL(vb_zero_kernel, dim3(1), dim3(64), 0, stream, a.ws);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

@@ -98,6 +98,15 @@ hipError_t launch_gemm(const GemmArgs<T>& a, bool pointer_form, hipStream_t stre
 template <typename T>
 int describe_gemm(const GemmArgs<T>& a, bool pointer_form, char* buf, int len);
 
+// Describe mode of the variable-size launchers (thread-local, set by
+// sbg_describe_vbatched): while buf is non-null a launcher writes the kernel
+// it would launch, its grid and its work units into buf and launches nothing.
+struct VbDescribe {
+    char* buf = nullptr;
+    int len = 0;
+};
+VbDescribe& vb_describe();
+
 // Variable-size form (per-matrix sizes in a.dm .. a.dldc, workspace a.ws of
 // vb_workspace_bytes(batch) bytes).
 template <typename T>

@@ -42,6 +42,7 @@ EXPORTS = [
     "sbg_sgemv_strided_batched", "sbg_dgemv_strided_batched", "sbg_cgemv_strided_batched",
     "sbg_zgemv_strided_batched", "sbg_strsm_strided_batched", "sbg_dtrsm_strided_batched",
     "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched", "sbg_gemm_vbatched_ex_noalloc", "sbg_tuned_table_info",
+    "sbg_describe_vbatched",
 ]
 
 
@@ -82,6 +83,9 @@ def load():
     lib.sbg_describe_strided.argtypes = [c_char, c_char, c_char, c_int, c_int, c_int, c_int, i64, c_int, i64,
                                          c_int, i64, i64, ctypes.c_char_p, c_int]
     lib.sbg_describe_strided.restype = c_int
+    lib.sbg_describe_vbatched.argtypes = [c_char, c_char, c_char, c_int, c_int, c_int, i64, c_int, c_int,
+                                          ctypes.c_char_p, c_int]
+    lib.sbg_describe_vbatched.restype = c_int
     for p in "sdcz":
         f = getattr(lib, f"sbg_{p}gemm_vbatched")
         f.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp,
@@ -338,6 +342,25 @@ def quantize_e4m3_vbatched(drows, dcols, max_rows, max_cols, Xptrs, dldx, Qptrs,
     if check:
         _check(st, "quantize_e4m3_vbatched")
     return st
+
+
+def describe_vbatched(prefix, transa, transb, max_m, max_n, max_k, batch, ab_type=0, mode=0):
+    """What a variable-size call would launch (nothing is launched): a dict
+    with "kernel" (demangled symbol), "grid" (work-groups of 4 waves),
+    "units" (wave steps; the upper bound for the binned MFMA path, which
+    also reports "u16", "u8", "u4"), or None if the call would not launch."""
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sbg_describe_vbatched(prefix.encode(), transa.encode(), transb.encode(), max_m, max_n, max_k, batch,
+                                      ab_type, mode, buf, 512)
+    if rc != 0:
+        return None
+    text = buf.value.decode()
+    kernel, _, rest = text.partition(") ")
+    out = {"kernel": kernel[len("kernel="):] + ")"}
+    for item in rest.split():
+        key, _, val = item.partition("=")
+        out[key] = int(val)
+    return out
 
 
 def describe_strided(prefix, transa, transb, m, n, k, lda, strideA, ldb, strideB, ldc, strideC, batch):

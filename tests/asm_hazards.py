@@ -13,7 +13,8 @@ import collections
 def min_wait_states(asm_text):
     """{kernel symbol: minimum wait states over all MFMA -> accumulator-read
     paths} (kernels without such a path are omitted)."""
-    names = re.findall(r'\n(_ZN3sbg\w+):', asm_text)
+    names = [n for n in re.findall(r'\n(_ZN3sbg\w+):', asm_text)
+             if re.search(r'\.type\s+' + re.escape(n) + r',@function', asm_text)]
     out = {}
     for name in names:
         i = asm_text.index('\n' + name + ':') + 1
@@ -87,3 +88,48 @@ def min_wait_states(asm_text):
         if kmin is not None:
             out[name] = kmin
     return out
+
+
+def _vregs(op):
+    m = re.match(r'v\[(\d+):(\d+)\]$', op)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    m = re.match(r'v(\d+)$', op)
+    return {int(m.group(1))} if m else set()
+
+
+def dpp_fma_hazards(asm_text):
+    """(count, violations) for the fused v_fmac_*_dpp statements: a DPP
+    source (src0) written by a VALU instruction fewer than two wait states
+    before, or a label (another predecessor) fewer than two wait states before,
+    is a violation.  Wait states count one per instruction and N + 1 per
+    s_nop N."""
+    lines = [l.split(';')[0].strip() for l in asm_text.splitlines()]
+    lines = [l for l in lines if l and not l.startswith('.') or re.match(r'^\.LBB\w+:', l or '')]
+    count, bad = 0, []
+    for i, l in enumerate(lines):
+        if not re.match(r'v_fmac_f(32|64)_dpp\s', l):
+            continue
+        count += 1
+        ops = [o.strip() for o in l.split(None, 1)[1].split(',')]
+        src = _vregs(ops[1].split()[0])
+        waits = 0
+        j = i - 1
+        while waits < 2 and j >= 0:
+            p = lines[j]
+            if re.match(r'^\.LBB\w+:', p):
+                bad.append((l, 'label', waits))
+                break
+            m = re.match(r's_nop\s+(\d+)', p)
+            if m:
+                waits += int(m.group(1)) + 1
+            else:
+                parts = p.split(None, 1)
+                if parts[0].startswith('v_') and len(parts) > 1:
+                    dst = _vregs(parts[1].split(',')[0].strip())
+                    if dst & src:
+                        bad.append((l, p, waits))
+                        break
+                waits += 1
+            j -= 1
+    return count, bad
