@@ -4,12 +4,12 @@
 // For matrix p: s_p = max |X_p| / 448 (448 = largest finite E4M3; s_p = 1 for
 // an all-zero matrix), Q_p = E4M3(X_p / s_p) rounded to nearest, ties to
 // even, saturating to +-448.  X_p ~= s_p * decode(Q_p); the GEMM applies s_A s_B
-// to the product.  One wavefront per matrix: 4 entries per lane, absmax by a
-// butterfly reduction across the wave.
+// to the product.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
+#include "gemm_vbteam.h"
 #include "sbg_internal.h"
 
 namespace sbg {
@@ -42,63 +42,155 @@ __device__ __forceinline__ unsigned char enc_e4m3(float v)
 }
 
 
+// Largest value of x over each row of 16 lanes (DPP row rotations).
+__device__ __forceinline__ float row16_max(float x)
+{
+#define SBG_ROR(N)                                                                                       \
+    x = fmaxf(x, __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x120 + (N), \
+                                                                    0xF, 0xF, false)));
+    SBG_ROR(8)
+    SBG_ROR(4)
+    SBG_ROR(2)
+    SBG_ROR(1)
+#undef SBG_ROR
+    return x;
+}
+
+// One team of 16 lanes per matrix (4 matrices per wave step, a persistent
+// grid over the batch): lane t loads column t (<= 16 rows) as 16-byte vectors
+// with every load issued before the first wait (the column loader of the
+// variable-size team kernel), the team's absmax comes from DPP row
+// rotations, and each lane encodes and stores its column.  A lane past the
+// matrix's columns, or a team with nothing to load, reads a valid dummy
+// address instead.
+// Sizes, leading dimensions and pointers of the matrix a team quantises
+// (read one step ahead, so the reads overlap the previous step).
+struct QuantMat {
+    const float* X;
+    unsigned char* Q;
+    int64_t ldx, ldq;
+    int rows, cols;
+    bool in;
+};
+
+template <bool VAR>
+__device__ __forceinline__ QuantMat quant_load(const QuantArgs& q, int64_t p0)
+{
+    QuantMat r;
+    r.in = p0 < q.batch;
+    const int64_t p = r.in ? p0 : q.batch - 1;
+    if (VAR) {
+        r.rows = q.drows[p];
+        r.cols = q.dcols[p];
+        r.ldx = q.dldx[p];
+        r.ldq = q.dldq[p];
+        r.X = q.Xarr[p];
+        r.Q = q.Qarr[p];
+    } else {
+        r.rows = q.rows;
+        r.cols = q.cols;
+        r.ldx = q.ldx;
+        r.ldq = q.ldq;
+        r.X = q.X + p * q.strideX;
+        r.Q = q.Q + p * q.strideQ;
+    }
+    return r;
+}
+
+// One team of 16 lanes per matrix (4 matrices per wave step, a persistent
+// grid over the batch): lane t loads column t (<= 16 rows) as 16-byte vectors
+// with every load issued before the first wait (the column loader of the
+// variable-size team kernel), the team's absmax comes from DPP row
+// rotations, and each lane encodes and stores its column.  A lane past the
+// matrix's columns, or a team with nothing to load, reads a valid dummy
+// address instead.
 template <bool VAR>
 __global__ __launch_bounds__(256) void quant_e4m3_kernel(const QuantArgs q)
 {
     const int lane = threadIdx.x & 63;
+    const int team = lane >> 4, t = lane & 15;
+    const int64_t steps = (q.batch + 3) / 4;
     const int64_t W = (int64_t)gridDim.x * 4;
-    for (int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < q.batch; p += W) {
-        int rows = q.rows, cols = q.cols;
-        int64_t ldx = q.ldx, ldq = q.ldq;
-        const float* X;
-        unsigned char* Q;
+    int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= steps) return;
+    QuantMat nx = quant_load<VAR>(q, g * 4 + team);
+    // the first reads complete before the loop, so that at its head the wait
+    // covers only the reads issued one step earlier
+    __asm__ volatile("" ::"v"(nx.rows), "v"(nx.cols), "v"(nx.ldx), "v"(nx.ldq), "v"(nx.X), "v"(nx.Q));
+    for (; g < steps; g += W) {
+        const QuantMat mt = nx;
+        const int64_t p = mt.in ? g * 4 + team : q.batch - 1;
+        nx = quant_load<VAR>(q, (g + W < steps ? g + W : g) * 4 + team);
+        const int rows = mt.rows, cols = mt.cols;
+        const int64_t ldx = mt.ldx, ldq = mt.ldq;
+        const float* X = mt.X;
+        unsigned char* Q = mt.Q;
+        bool ok = mt.in;
         if (VAR) {
-            rows = q.drows[p];
-            cols = q.dcols[p];
-            ldx = q.dldx[p];
-            ldq = q.dldq[p];
-            X = q.Xarr[p];
-            Q = q.Qarr[p];
-            if (rows < 0 || cols < 0 || rows > q.max_rows || cols > q.max_cols || ldx < (rows > 1 ? rows : 1) ||
-                ldq < (rows > 1 ? rows : 1))
-                continue;   // invalid sizes: matrix skipped (its scale is not written)
-        } else {
-            X = q.X + p * q.strideX;
-            Q = q.Q + p * q.strideQ;
+            // invalid sizes: the matrix is skipped (its scale is not written)
+            ok = ok && !(rows < 0 || cols < 0 || rows > q.max_rows || cols > q.max_cols ||
+                         ldx < (rows > 1 ? rows : 1) || ldq < (rows > 1 ? rows : 1));
         }
-        const int cnt = rows * cols;
-        float v[4];
-        int ri[4], ci[4];
+        const bool has = ok && rows > 0 && cols > 0;
+        const bool mine = has && t < cols;
+        // the dummy: the matrix's row count (variable-size) or its first column
+        const GBy dummy = VAR ? gby(q.drows + p) : gby(X);
+        const GBy col = mine ? gby(X + (int64_t)t * ldx) : dummy;
+        const int L = mine ? rows * 4 : 4;
+        VbCol<4> r;
+        vb_issue<4>(r, col, L);
+        vb_u4 x[4];
+        vb_fix<4, false>(x, r, col, L);
+        float v[16];
         float amax = 0.f;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int e = lane + 64 * t;
-            v[t] = 0.f;
-            ri[t] = 0;
-            ci[t] = 0;
-            if (e < cnt) {
-                ri[t] = e % rows;
-                ci[t] = e / rows;
-                v[t] = X[ri[t] + ldx * ci[t]];
-                amax = fmaxf(amax, fabsf(v[t]));
-            }
+        for (int e = 0; e < 16; ++e) {
+            const unsigned w = e % 4 == 0 ? x[e / 4].x : (e % 4 == 1 ? x[e / 4].y : (e % 4 == 2 ? x[e / 4].z : x[e / 4].w));
+            v[e] = (mine && e < rows) ? __uint_as_float(w) : 0.f;
+            amax = fmaxf(amax, fabsf(v[e]));
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+        amax = row16_max(amax);
         const float s = amax > 0.f ? amax / 448.0f : 1.0f;
+        float qv[16];
+        bool wide = false;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int e = lane + 64 * t;
-            if (e < cnt) Q[ri[t] + ldq * ci[t]] = enc_e4m3(v[t] / s);
+        for (int e = 0; e < 16; ++e) {
+            qv[e] = v[e] / s;
+            wide = wide || !(fabsf(qv[e]) < 464.0f);   // NaN too
         }
-        if (lane == 0) q.scales[p] = s;
+        // The hardware conversion (round to nearest even) gives the same codes
+        // as enc_e4m3 for every binary32 value of magnitude below 464 (checked
+        // exhaustively on the device); quotients of finite inputs never
+        // exceed 448 (1 + 2^-23).  A wave holding a larger value or a NaN
+        // (non-finite inputs) takes the software encoder.
+        unsigned codes[4];
+        if (__builtin_amdgcn_ballot_w64(wide) == 0) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d], qv[4 * d + 1], 0, false);
+                codes[d] = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d + 2], qv[4 * d + 3], lo, true);
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                codes[d] = (unsigned)enc_e4m3(qv[4 * d]) | ((unsigned)enc_e4m3(qv[4 * d + 1]) << 8) |
+                           ((unsigned)enc_e4m3(qv[4 * d + 2]) << 16) | ((unsigned)enc_e4m3(qv[4 * d + 3]) << 24);
+        }
+        if (mine) {
+            unsigned char* qc = Q + (int64_t)t * ldq;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (e < rows) qc[e] = (unsigned char)(codes[e >> 2] >> (8 * (e & 3)));
+        }
+        if (ok && t == 0) q.scales[p] = s;   // an empty matrix gets scale 1
     }
 }
 
 hipError_t launch_quant_e4m3(const QuantArgs& q, bool var, hipStream_t stream)
 {
-    int64_t grid = (q.batch + 3) / 4;
-    const int64_t cap = (int64_t)device_cu_count() * 8;
+    const int64_t steps = (q.batch + 3) / 4;
+    int64_t grid = (steps + 3) / 4;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
     if (var)

@@ -87,6 +87,66 @@ def test_quantiser_matches_oracle_bitwise(gpu_lib):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "logu"])
+def test_quantiser_vbatched_matches_oracle_bitwise(gpu_lib, dist):
+    """Variable-size quantiser: sizes 0..16 drawn per matrix, padded leading
+    dimensions on both sides (NaN in the gaps of X), an all-zero matrix, and
+    two rejected matrices (rows above the bound; ldq too small), whose codes
+    and scale stay untouched.  Codes and scales bit for bit against the oracle;
+    the bytes between Q's columns are left alone."""
+    g = inputs.rng(4, salt=12 if dist == "uniform" else 13)
+    N = 2001
+    rows = g.integers(0, 17, size=N).astype(np.int32)
+    cols = g.integers(0, 17, size=N).astype(np.int32)
+    rows[:3] = 16
+    cols[:3] = 16
+    rows[7] = max(int(rows[7]), 2)
+    ldx = (np.maximum(rows, 1) + g.integers(0, 3, size=N)).astype(np.int32)
+    ldq = (np.maximum(rows, 1) + g.integers(0, 2, size=N)).astype(np.int32)
+    bad = np.zeros(N, dtype=bool)
+    ldq[7], bad[7] = int(rows[7]) - 1, True     # leading dimension of Q too small
+    sizeX = np.maximum(ldx.astype(np.int64) * cols, 1)
+    sizeQ = np.maximum(ldq.astype(np.int64) * cols, 1)
+    offX = np.concatenate([[0], np.cumsum(sizeX)[:-1]])
+    offQ = np.concatenate([[0], np.cumsum(sizeQ)[:-1]])
+    X = np.full(int(sizeX.sum()), np.nan, dtype=np.float32)
+    for p in range(N):
+        r, c = int(rows[p]), int(cols[p])
+        if r and c:
+            idx = offX[p] + np.arange(c)[:, None] * ldx[p] + np.arange(r)[None, :]
+            X[idx] = inputs.DISTS[dist](g, (c, r), np.float32)
+    X[offX[1] + np.arange(int(ldx[1]) * int(cols[1]))] = 0.0    # matrix 1: all zero (scale 1)
+    rows_dev = rows.copy()
+    rows_dev[5], bad[5] = 17, True              # above max_rows
+    dX = to_dev(X)
+    dQ = torch.full((int(sizeQ.sum()),), 0xAB, dtype=torch.uint8, device="cuda")
+    dS = torch.full((N,), -7.0, dtype=torch.float32, device="cuda")
+    pX = torch.tensor(dX.data_ptr() + offX * 4, device="cuda")
+    pQ = torch.tensor(dQ.data_ptr() + offQ, device="cuda")
+    say(f"quantise variable-size N={N} {dist}")
+    sbg.quantize_e4m3_vbatched(torch.from_numpy(rows_dev).cuda(), torch.from_numpy(cols).cuda(), 16, 16, pX,
+                               torch.from_numpy(ldx).cuda(), pQ, torch.from_numpy(ldq).cuda(), dS, N)
+    torch.cuda.synchronize()
+    Qg, Sg = from_dev(dQ), from_dev(dS)
+    good = np.nonzero(~bad)[0]
+    Qo, offO, So = oracle.quant_e4m3(X, offX[good], rows[good], cols[good], ldx[good], len(good))
+    for q, p in enumerate(good):
+        r, c = int(rows[p]), int(cols[p])
+        got = Qg[offQ[p] + np.arange(c)[:, None] * ldq[p] + np.arange(r)[None, :]]
+        ref = Qo[offO[q]:offO[q] + r * c].reshape(c, r)
+        assert np.array_equal(got, ref), p
+        assert Sg[p] == (So[q] if r and c else 1.0), (p, Sg[p], So[q])
+    for p in np.nonzero(bad)[0]:
+        assert Sg[p] == -7.0, p
+        assert np.all(Qg[offQ[p]:offQ[p] + sizeQ[p]] == 0xAB), p
+    # the gaps between columns (ldq > rows) keep their bytes
+    mask = np.ones(Qg.size, dtype=bool)
+    for p in good:
+        r, c = int(rows[p]), int(cols[p])
+        mask[offQ[p] + np.arange(c)[:, None] * ldq[p] + np.arange(r)[None, :]] = False
+    assert np.all(Qg[mask] == 0xAB)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "logu"])
 def test_fp8_scaled_strided(gpu_lib, dist):
     g = inputs.rng(4, salt=12)
     for (ta, tb, s) in [("N", "N", 16), ("T", "N", 8), ("N", "T", 3), ("T", "T", 11)]:
