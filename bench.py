@@ -769,8 +769,10 @@ def sec_blas_routines(stream):
     batched GEMM, the paper's outlook): GEMV y = 1.5 op(A) x - 0.5 y with A
     16 x 16, N = 10^6, ops N and T; TRSM op(A) X = 1.5 B with A 16 x 16 lower,
     16 right-hand sides, N = 200,000, and a blocked order-64 case (N =
-    20,000).  HBM bytes: GEMV A + x + y read + y written; TRSM the triangle of
-    A + B read + B written."""
+    20,000); LU with partial pivoting of order 4, 8, 16 (N = 100,000) and 32
+    (N = 50,000).  HBM bytes: GEMV A + x + y read + y written; TRSM the
+    triangle of A + B read + B written; LU A read and written plus the
+    interchanges and info."""
     import torch
 
     from paper_1304_7053_amd import sbg, timing
@@ -801,6 +803,18 @@ def sec_blas_routines(stream):
                                                "gflops": round(1.0 * s * s * 16 * N / t / 1e9, 1),
                                                "hbm_frac": round(byts / t / HBM_PEAK, 4)}
             del A, B
+        # LU with partial pivoting, in place (repeated factorisations of the
+        # factors time the same work); flops 2 n^3 / 3 per matrix
+        for s, N in ((4, 100_000), (8, 100_000), (16, 100_000), (32, 50_000)):
+            A = _rand(gen, N * s * s, tdt)
+            ipiv = torch.empty(N * s, dtype=torch.int32, device="cuda")
+            info = torch.empty(N, dtype=torch.int32, device="cuda")
+            t = _med(lambda i: sbg.getrf_strided(s, A, s, s * s, ipiv, s, info, N), 7, flush)
+            byts = N * (2 * s * s * esz + 4 * s + 4)
+            out[f"getrf_{tname}_{s}"] = {"N": N, "us": round(t * 1e6, 1),
+                                         "gflops": round(2.0 * s ** 3 / 3 * N / t / 1e9, 1),
+                                         "hbm_frac": round(byts / t / HBM_PEAK, 4)}
+            del A, ipiv, info
     return out
 
 

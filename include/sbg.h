@@ -350,6 +350,24 @@ int sbg_set_tuning(const char* key, int value);
 int sbg_get_tuning(const char* key);
 int sbg_tuned_table_info(char* buf, int buflen);
 
+/* ---- batched LU factorisation with partial pivoting (n <= 32) -------------
+ * LAPACK GETRF on each n x n matrix A_p = A + strideA p (column-major, lda):
+ * P_p A_p = L_p U_p, the largest magnitude on and below the diagonal chosen as
+ * pivot in each column (the first on ties).  The factors overwrite A_p (L
+ * unit lower, its ones not stored; U upper), ipiv[strideP p + k] (1-based) is
+ * the row interchanged with row k at step k, and info[p] is 0, or the 1-based
+ * index of the first exactly zero pivot (the factorisation still completes;
+ * U is singular).  The paper proposes building further batched routines on
+ * its batched interface (Sec. 9); this is the LU of that family.
+ * Positions: 1 n (> 32: SBG_NOT_SUPPORTED), 2 A, 3 lda (>= max(1, n)),
+ * 4 strideA (>= lda * n when batch_count > 1), 5 ipiv, 6 strideP (>= n when
+ * batch_count > 1), 7 info, 8 batch_count, 9 stream.  n == 0 sets every
+ * info[p] to 0; batch_count == 0 returns at once. */
+sbg_status_t sbg_sgetrf_strided_batched(int n, float* A, int lda, int64_t strideA, int* ipiv, int64_t strideP,
+    int* info, int64_t batch_count, void* stream);
+sbg_status_t sbg_dgetrf_strided_batched(int n, double* A, int lda, int64_t strideA, int* ipiv, int64_t strideP,
+    int* info, int64_t batch_count, void* stream);
+
 /* ---- diagnostics --------------------------------------------------------
  * sbg_describe_strided: validates the arguments of a strided call (prefix
  *   's', 'd', 'c' or 'z' selects the entry point; alpha = 1, beta = 0.5 are

@@ -480,6 +480,35 @@ sbg_status_t gemv(char trans, int m, int n, const typename Scal<T>::api_t* alpha
 // Positions: 1 side, 2 uplo, 3 transa, 4 diag, 5 m, 6 n, 7 alpha, 8 A, 9 lda,
 // 10 strideA, 11 B, 12 ldb, 13 strideB, 14 batch_count.
 template <typename T>
+sbg_status_t getrf(int n, void* A, int lda, int64_t sA, int* ipiv, int64_t sP, int* info, int64_t batch,
+                   void* stream)
+{
+    tl_last_invalid = 0;
+    if (n < 0) return reject(1);
+    if (n > 32) return SBG_NOT_SUPPORTED;
+    const bool nonempty = n > 0 && batch > 0;
+    if (nonempty && !A) return reject(2);
+    if (lda < (n > 1 ? n : 1)) return reject(3);
+    if (sA < 0 || (batch > 1 && sA < (int64_t)lda * n)) return reject(4);
+    if (nonempty && !ipiv) return reject(5);
+    if (sP < 0 || (batch > 1 && sP < n)) return reject(6);
+    if (batch > 0 && !info) return reject(7);
+    if (batch < 0) return reject(8);
+    if (batch == 0) return SBG_OK;
+    GetrfArgs<T> g{};
+    g.n = n;
+    g.A = static_cast<T*>(A);
+    g.lda = lda;
+    g.strideA = sA;
+    g.ipiv = ipiv;
+    g.strideP = sP;
+    g.info = info;
+    g.batch = batch;
+    // n == 0 still launches: every info[p] is set to 0
+    return launch_getrf<T>(g, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? SBG_OK : SBG_HIP_ERROR;
+}
+
+template <typename T>
 sbg_status_t trsm(char side, char uplo, char transa, char diag, int m, int n,
                   const typename Scal<T>::api_t* alpha, const void* A, int lda, int64_t sA, void* B, int ldb,
                   int64_t sB, int64_t batch, void* stream)
@@ -654,6 +683,18 @@ sbg_status_t sbg_sgemv_strided_batched(char trans, int m, int n, const float* al
 {
     return sbg::gemv<float>(trans, m, n, alpha, A, lda, strideA, x, incx, stridex, beta, y, incy, stridey,
                             batch_count, stream);
+}
+
+sbg_status_t sbg_sgetrf_strided_batched(int n, float* A, int lda, int64_t strideA, int* ipiv, int64_t strideP,
+                                        int* info, int64_t batch_count, void* stream)
+{
+    return sbg::getrf<float>(n, A, lda, strideA, ipiv, strideP, info, batch_count, stream);
+}
+
+sbg_status_t sbg_dgetrf_strided_batched(int n, double* A, int lda, int64_t strideA, int* ipiv, int64_t strideP,
+                                        int* info, int64_t batch_count, void* stream)
+{
+    return sbg::getrf<double>(n, A, lda, strideA, ipiv, strideP, info, batch_count, stream);
 }
 
 sbg_status_t sbg_strsm_strided_batched(char side, char uplo, char transa, char diag, int m, int n,

@@ -166,4 +166,22 @@ struct TrsmArgs {
 template <typename T>
 hipError_t launch_trsm_small(const TrsmArgs<T>& a, hipStream_t stream);
 
+// Batched LU with partial pivoting of n x n matrices (n <= 64), a strided
+// batch: A_p at A + strideA p (column-major, lda), factors in place,
+// interchanges ipiv[strideP p + k] (1-based) and info[p] (0, or the 1-based
+// index of the first zero pivot).
+template <typename T>
+struct GetrfArgs {
+    int n;
+    T* A;
+    int64_t lda, strideA;
+    int* ipiv;
+    int64_t strideP;
+    int* info;
+    int64_t batch;
+};
+
+template <typename T>
+hipError_t launch_getrf(const GetrfArgs<T>& g, hipStream_t stream);
+
 }  // namespace sbg

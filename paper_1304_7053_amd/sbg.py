@@ -42,7 +42,7 @@ EXPORTS = [
     "sbg_sgemv_strided_batched", "sbg_dgemv_strided_batched", "sbg_cgemv_strided_batched",
     "sbg_zgemv_strided_batched", "sbg_strsm_strided_batched", "sbg_dtrsm_strided_batched",
     "sbg_ctrsm_strided_batched", "sbg_ztrsm_strided_batched", "sbg_gemm_vbatched_ex_noalloc", "sbg_tuned_table_info",
-    "sbg_describe_vbatched",
+    "sbg_describe_vbatched", "sbg_sgetrf_strided_batched", "sbg_dgetrf_strided_batched",
 ]
 
 
@@ -86,6 +86,10 @@ def load():
     lib.sbg_describe_vbatched.argtypes = [c_char, c_char, c_char, c_int, c_int, c_int, i64, c_int, c_int,
                                           ctypes.c_char_p, c_int]
     lib.sbg_describe_vbatched.restype = c_int
+    for p in "sd":
+        f = getattr(lib, f"sbg_{p}getrf_strided_batched")
+        f.argtypes = [c_int, vp, c_int, i64, vp, i64, vp, i64, vp]
+        f.restype = c_int
     for p in "sdcz":
         f = getattr(lib, f"sbg_{p}gemm_vbatched")
         f.argtypes = [c_char, c_char, vp, vp, vp, c_int, c_int, c_int, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp,
@@ -341,6 +345,18 @@ def quantize_e4m3_vbatched(drows, dcols, max_rows, max_cols, Xptrs, dldx, Qptrs,
                                            _stream(stream))
     if check:
         _check(st, "quantize_e4m3_vbatched")
+    return st
+
+
+def getrf_strided(n, A, lda, strideA, ipiv, strideP, info, batch, stream=None, check=True):
+    """Batched LU with partial pivoting of the n x n matrices A_p at
+    A + strideA p (float32 or float64 tensor, in place); ipiv and info are
+    int32 tensors (1-based interchanges; 0 or the first zero pivot)."""
+    p = {torch.float32: "s", torch.float64: "d"}[A.dtype]
+    st = getattr(load(), f"sbg_{p}getrf_strided_batched")(n, _dptr(A), lda, strideA, _dptr(ipiv), strideP,
+                                                         _dptr(info), batch, _stream(stream))
+    if check:
+        _check(st, "getrf_strided")
     return st
 
 

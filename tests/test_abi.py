@@ -258,3 +258,26 @@ def test_trsm_quick_returns(prefix):
     assert _trsm(prefix, m=0, A=None, B=None) == sbg.SBG_OK
     assert _trsm(prefix, n=0, A=None, B=None, sB=0) == sbg.SBG_OK
     assert _trsm(prefix, batch=0, A=None, B=None) == sbg.SBG_OK
+
+
+def _getrf(prefix, n=4, A=1, lda=4, sA=16, ipiv=1, sP=4, info=1, batch=2):
+    L = sbg.load()
+    f = getattr(L, f"sbg_{prefix}getrf_strided_batched")
+    return f(n, A, lda, sA, ipiv, sP, info, batch, None)
+
+
+@pytest.mark.parametrize("prefix", "sd")
+@pytest.mark.parametrize("kw,pos", [
+    (dict(n=-1), 1), (dict(A=None), 2), (dict(lda=3), 3), (dict(sA=-1), 4), (dict(sA=15), 4),
+    (dict(ipiv=None), 5), (dict(sP=3), 6), (dict(sP=-1), 6), (dict(info=None), 7), (dict(batch=-1), 8),
+    (dict(n=-1, A=None), 1),
+])
+def test_getrf_invalid_arguments_rejected_in_order(prefix, kw, pos):
+    assert _getrf(prefix, **kw) == sbg.SBG_INVALID_VALUE
+    assert sbg.last_invalid_arg() == pos
+
+
+@pytest.mark.parametrize("prefix", "sd")
+def test_getrf_limits_and_quick_return(prefix):
+    assert _getrf(prefix, n=33, lda=33, sA=33 * 33, sP=33) == sbg.SBG_NOT_SUPPORTED
+    assert _getrf(prefix, batch=0, A=None, ipiv=None, info=None) == sbg.SBG_OK
