@@ -161,6 +161,7 @@ def main():
         step()
     torch.cuda.synchronize()
     g_step = _graph(step, stream)
+    print(f"bench: {len(calls)} calls per step captured", file=sys.stderr, flush=True)
 
     # timed region: K steps, one graph replay each
     torch.cuda.synchronize()
@@ -236,11 +237,13 @@ def main():
         for name, fn in sections:
             if only and name not in only:
                 continue
+            t_sec = time.perf_counter()
             try:
                 secondary[name] = fn(stream)
             except Exception as e:  # a secondary failure must not hide the primary line
                 secondary[name] = {"error": f"{type(e).__name__}: {e}"}
             torch.cuda.empty_cache()
+            print(f"bench: section {name} done in {time.perf_counter() - t_sec:.1f} s", file=sys.stderr, flush=True)
 
     cpu = None
     if cpu_sample:

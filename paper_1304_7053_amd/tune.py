@@ -12,6 +12,8 @@ Here every choice the library makes per call is measured on the device:
     or team kernel (sizes <= 8, and <= 16 for real types);
   * for the persistent kernels: the tile unroll U, the work-groups per CU and
     the XCD run length (coordinate search in that order);
+  * a key whose best choice is not at least 3% faster than the built-in rules
+    keeps the rules (entry path "rule");
 
 and the launch-shape (grid-size) sweep itself is recorded beside the table.
 
@@ -44,6 +46,7 @@ MIN_SET_BYTES = 768 << 20          # rotate buffers until this much is touched
 MAX_TOTAL_BYTES = 6 << 30
 TYPES = {"s": torch.float32, "d": torch.float64, "c": torch.complex64, "z": torch.complex128}
 PATH_NAME = {1: "mfma", 2: "team", 3: "staged"}
+MARGIN = 0.97          # a tuned choice must beat the built-in rules by 3%
 
 
 def stored(op, rows, cols):
@@ -139,6 +142,11 @@ def tune_key(w, ops, form, reps):
             t = measure(w, ops, form, dict(kn, xcd_chunk=xc), reps)
             if t < us:
                 us, entry["xcd_chunk"] = t, xc
+    if us > MARGIN * default:
+        # not clearly ahead of the built-in rules: keep them (a choice inside
+        # the timing noise would only add run-to-run variation)
+        entry = {"path": "rule", "unroll": 0, "wg_per_cu": 0, "xcd_chunk": 0}
+        us = default
     esz = torch.empty(0, dtype=TYPES[prefix]).element_size()
     algo = 4 * s * s * esz * w.batch + (24 * w.batch if form == "pointer" else 0)
     entry.update({"type": prefix, "form": form, "ops": ops, "size": s, "us": round(us, 3),

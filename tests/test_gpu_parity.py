@@ -255,6 +255,27 @@ def test_full_size_complex(gpu_lib, dtype):
                 check(c, c.run_gpu(), idx=idx, label="fullsize-c")
 
 
+@pytest.mark.parametrize("dtype", ALL, ids=lambda d: np.dtype(d).name)
+def test_shared_operand_every_class(gpu_lib, dtype):
+    """One A or one B for the whole batch (stride 0): every size class, op
+    pair and shared side, batches long enough that every wave runs several
+    tiles, through whatever kernel the library picks."""
+    g = inputs.rng(208)
+    al, be = scalars(dtype)
+    ops = "NTC" if np.dtype(dtype).kind == "c" else "NT"
+    for (m, n, k) in ((3, 4, 2), (8, 8, 8), (7, 5, 6), (16, 16, 16), (13, 5, 11)):
+        for ta in ops:
+            for tb in ops:
+                for shared in "AB":
+                    c = Case(dtype, ta, tb, m, n, k, 5003, al, be, g)
+                    if shared == "A":
+                        c.sA = 0
+                    else:
+                        c.sB = 0
+                    say(f"shared {shared} {np.dtype(dtype).name} {ta}{tb} {m}x{n}x{k}")
+                    check(c, c.run_gpu(), label=f"shared{shared}")
+
+
 @pytest.mark.parametrize("dtype", REAL, ids=lambda d: np.dtype(d).name)
 def test_full_size_fixed_operand(gpu_lib, dtype):
     """The fixed-operand case (Sec. 9 outlook): one A (strideA = 0) or one B
