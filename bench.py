@@ -213,7 +213,8 @@ def main():
     sizes_out = {k: {"gflops": round(v[0] / v[2] / 1e9, 1), "hbm_frac": round(v[1] / v[2] / HBM_PEAK, 4)}
                  for k, v in per_size.items()}
     kernels_out = {k: {"launches": v["launches"], "mean_us": round(v["s"] / v["launches"] * 1e6, 3),
-                       "hbm_frac": round(v["bytes"] / v["s"] / HBM_PEAK, 4)} for k, v in per_kernel.items()}
+                       "hbm_frac": round(v["bytes"] / v["s"] / HBM_PEAK, 4),
+                       "algorithmic_bytes_per_launch": v["bytes"] / v["launches"]} for k, v in per_kernel.items()}
 
     cpu_calls = calls if not args.no_cpu_baseline else None
     cpu_sample = [dict(n=c["n"], ops=c["ops"], A=c["A"][:args.cpu_sample * c["n"] ** 2].cpu(),
@@ -580,8 +581,10 @@ def sec_varsize_modes(stream, samples):
             med = _med(lambda i: gr.replay(), 7, flush)
             byts = float(np.sum((m64 * k64 + k64 * n64) * esz + 2 * m64 * n64 * 4)) + N * meta + \
                 (8 * N if mode == "e4m3" else 0)
+            plan = sbg.describe_vbatched("s", "N", "N", 16, 16, 16, N, code, cmode)
             results[mode] = {"us": round(med * 1e6, 1), "gflops": round(flops / med / 1e9, 1),
-                             "hbm_frac": round(byts / med / HBM_PEAK, 4)}
+                             "hbm_frac": round(byts / med / HBM_PEAK, 4), "algorithmic_bytes": byts,
+                             "kernel": plan["kernel"] if plan else None}
             if qtime is not None:
                 results[mode]["quantize_us"] = round(qtime * 1e6, 1)
             del gr
@@ -762,7 +765,11 @@ def sec_large_sizes(stream):
                                                     n, n * n, N), 5, flush)
                 out[f"{tname}_n{n}_{ops}"] = {"N": N, "us": round(t * 1e6, 1),
                                                "gflops": round(2.0 * n ** 3 * N / t / 1e9, 1),
-                                               "hbm_frac": round(4.0 * esz * el / t / HBM_PEAK, 4)}
+                                               "hbm_frac": round(4.0 * esz * el / t / HBM_PEAK, 4),
+                                               "algorithmic_bytes": 4.0 * esz * el,
+                                               "kernel": sbg.describe_strided("s" if esz == 4 else "d", ops[0],
+                                                                              ops[1], n, n, n, n, n * n, n, n * n,
+                                                                              n, n * n, N)}
             del A, B, C
     return out
 
