@@ -298,7 +298,7 @@ def timing_per_call(calls, launch, passes):
     for _ in range(passes):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in calls]
         torch.cuda.synchronize()
-        timing.spin(len(calls) * 70.0 + 200.0)
+        timing.spin(len(calls) * 300.0 + 1000.0)   # longer than enqueueing the pass, also under a tracer
         for c, (e0, e1) in zip(calls, evs):
             e0.record(stream)
             launch(c)

@@ -337,10 +337,15 @@ int sbg_version(void);
  *                 direct kernel's unroll when neither the knob nor the table
  *                 does (size classes 4/8 and 16; 256..2^20; the class-16
  *                 budget is for 4-byte elements and scales with the size);
- *   "pipeline"    0/1: prefetch the next tile group in the direct kernel.
+ *   "pipeline"    0/1: prefetch the next tile group in the direct kernel;
+ *   "blocked"     sizes above 16 (real types): 0 automatic (the LDS-staged
+ *                 sub-blocked kernel where it measured faster), 1 the register
+ *                 sub-blocked kernel only, 2 the LDS-staged kernel wherever it
+ *                 applies (m, n, k <= 64 and leading dimensions of A and B
+ *                 whose byte size is a multiple of 16).
  * Environment variables SBG_WG_PER_CU, SBG_XCD_CHUNK, SBG_STAGED, SBG_PATH,
- * SBG_UNROLL, SBG_GRID, SBG_TABLE, SBG_TILE_BYTES, SBG_TILE_BYTES16 and
- * SBG_PIPELINE set the initial values.
+ * SBG_UNROLL, SBG_GRID, SBG_TABLE, SBG_TILE_BYTES, SBG_TILE_BYTES16,
+ * SBG_BLOCKED and SBG_PIPELINE set the initial values.
  * sbg_set_tuning returns the previous value, or -1 for an unknown key or an
  * out-of-range value (nothing changed); sbg_get_tuning returns the value or -1.
  * sbg_tuned_table_info writes "file=<path> version=<v> entries=<count>" into

@@ -54,7 +54,7 @@ int resident_blocks_per_cu(const void* kernel)
 Tuning& tuning_mut()
 {
     static Tuning t = [] {
-        Tuning v{0, 0, 2, 2048, 8192, false, 0, 0, 0, 1};
+        Tuning v{0, 0, 2, 2048, 8192, false, 0, 0, 0, 1, 0};
         const auto env = [](const char* name, int lo, int hi, int& dst) {
             if (const char* e = std::getenv(name)) {
                 const int x = std::atoi(e);
@@ -70,6 +70,7 @@ Tuning& tuning_mut()
         env("SBG_UNROLL", 0, 8, v.unroll);
         env("SBG_GRID", 0, 1 << 20, v.grid);
         env("SBG_TABLE", 0, 1, v.table);
+        env("SBG_BLOCKED", 0, 2, v.blocked);
         if (const char* e = std::getenv("SBG_PIPELINE")) v.pipeline = std::atoi(e) != 0;
         return v;
     }();
@@ -1062,6 +1063,7 @@ const Knob kKnobs[] = {
     {"unroll", 0, 8, &sbg::Tuning::unroll},
     {"grid", 0, 1 << 20, &sbg::Tuning::grid},
     {"table", 0, 1, &sbg::Tuning::table},
+    {"blocked", 0, 2, &sbg::Tuning::blocked},
 };
 }  // namespace
 

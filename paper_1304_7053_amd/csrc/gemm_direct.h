@@ -443,18 +443,17 @@ template <> struct TypeName<bf16_t> { static constexpr const char* s = "sbg::bf1
 template <> struct TypeName<f16_t> { static constexpr const char* s = "sbg::f16_t"; };
 template <> struct TypeName<e4m3_t> { static constexpr const char* s = "sbg::e4m3_t"; };
 
+// The kernel symbol of a call above size 16 (gemm_blocked.h).
+template <typename T>
+int describe_blocked(const GemmArgs<T>& a, bool pointer_form, char* buf, int len);
+
 // The kernel symbol (as profilers demangle it) a plain launch with these
 // arguments uses, written into buf.
 template <typename T>
 int describe_gemm_impl(GemmArgs<T> a, bool pointer_form, char* buf, int len)
 {
     const auto tf = [](bool b) { return b ? "true" : "false"; };
-    if (a.m > 16 || a.n > 16 || a.k > 16) {
-        const int nkc = (a.k + 15) / 16;
-        const int U = nkc <= 1 ? 1 : (nkc <= 2 || Tr<T>::cplx ? 2 : 4);
-        return snprintf(buf, len, "void sbg::gemm_blocked_kernel<%s, %d, %s, %s, %s>(sbg::GemmArgs<%s>)",
-                        TypeName<T>::s, U, tf(a.a_trans), tf(!a.b_trans), tf(pointer_form), TypeName<T>::s);
-    }
+    if (a.m > 16 || a.n > 16 || a.k > 16) return describe_blocked<T>(a, pointer_form, buf, len);
     const Kern kind = plan_gemm<T, T, 0>(a, pointer_form);
     const int D = size_class(a.m, a.n, a.k);
     if (kind == Kern::Team)

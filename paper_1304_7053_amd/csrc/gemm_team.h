@@ -162,7 +162,7 @@ __device__ __forceinline__ int64_t xcd_block_index()
     return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
-// D: size class (4 or 8, bounds m, n, k); AC / BC: op(A) / op(B) is N or R
+// D: size class (4, 8, or 16 for the real types; bounds m, n, k); AC / BC: op(A) / op(B) is N or R
 // (a stored column is a column of the operand) rather than T or C (a stored
 // column is a row of the operand); VEC: every column a lane loads or stores
 // holds at least one 16-byte vector (loaded as vectors), else element by

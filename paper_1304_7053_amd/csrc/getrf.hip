@@ -1,18 +1,16 @@
 // Batched LU factorisation with partial pivoting (LAPACK GETRF semantics) of
-// small square matrices (n <= 64), a strided batch.  The paper proposes
+// small square matrices (n <= 32), a strided batch.  The paper proposes
 // carrying its batched interface over to other batched BLAS / LAPACK kernels
 // (Sec. 9); this is the first of them beside GEMV and TRSM.
 //
-// One team of D lanes per matrix (D = 4, 8, 16, 32 or 64 >= n; 64 / D
+// One team of D lanes per matrix (D = 4, 8, 16 or 32 >= n; 64 / D
 // matrices per wave), ROW per lane: lane t holds row t of the matrix in
 // registers for the whole factorisation, so no row is ever moved.  Step k:
 //   1. the eligible rows (not yet pivots) offer |a_t[k]|; a team reduction
 //      (shuffles) picks the largest, the lowest current position on ties --
 //      LAPACK's choice, which takes the first maximum of the interchanged
 //      matrix;
-//   2. the pivot row is broadcast to the team: through LDS for teams of up
-//      to 32 lanes, by lane reads into scalar registers for a team that is
-//      the whole wave;
+//   2. the pivot row is broadcast to the team through the team's LDS slot;
 //   3. every other eligible row forms its multiplier a_t[k] / pivot (an
 //      IEEE division; unscaled when the pivot is zero) and updates
 //      a_t[j] -= l_t u_j for j > k (FMA);
@@ -49,29 +47,10 @@ __device__ __forceinline__ void team_argmax(T& v, int& cur, int& lane)
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T bcast_lane(T x, int lane);
-
-template <>
-__device__ __forceinline__ float bcast_lane<float>(float x, int lane)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
-}
-
-template <>
-__device__ __forceinline__ double bcast_lane<double>(double x, int lane)
-{
-    const long long v = __builtin_bit_cast(long long, x);
-    const int lo = __builtin_amdgcn_readlane((int)v, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
 template <typename T, int D>
 __global__ __launch_bounds__(256) void getrf_kernel(const GetrfArgs<T> g)
 {
     constexpr int TPW = 64 / D;
-    constexpr bool WAVE = D == 64;
     __shared__ __attribute__((aligned(16))) T lds[4 * 64];
     const int lane = threadIdx.x & 63;
     const int team = lane / D, t = lane - team * D;
@@ -108,41 +87,28 @@ __global__ __launch_bounds__(256) void getrf_kernel(const GetrfArgs<T> g)
         const bool upd = elig && lane != plane;   // rows that take a multiplier
         // 2. the pivot row to every lane of the team, 3. multipliers and
         // the trailing update (the pivot row itself is not changed in step k)
-        T piv, l = T(0);
-        if constexpr (WAVE) {
-            const int pl = __builtin_amdgcn_readfirstlane(plane);
-            piv = bcast_lane<T>(a[k], pl);
-            if (upd) l = piv != T(0) ? a[k] / piv : a[k];
+        if (lane == plane) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                if (j > k) {
-                    const T uj = bcast_lane<T>(a[j], pl);
-                    if (upd) a[j] = __builtin_fma(-l, uj, a[j]);
-                }
-            }
-        } else {
-            if (lane == plane) {
-#pragma unroll
-                for (int j = 0; j < D; ++j)
-                    if (j >= k) slot[j] = a[j];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            piv = slot[k];
-            if (upd) l = piv != T(0) ? a[k] / piv : a[k];
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                if (j > k) {
-                    const T uj = slot[j];
-                    if (upd) a[j] = __builtin_fma(-l, uj, a[j]);
-                }
-            }
-            // the slot is rewritten in the next step only after every lane read it
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int j = 0; j < D; ++j)
+                if (j >= k) slot[j] = a[j];
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const T piv = slot[k];
+        T l = T(0);
+        if (upd) l = piv != T(0) ? a[k] / piv : a[k];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j > k) {
+                const T uj = slot[j];
+                if (upd) a[j] = __builtin_fma(-l, uj, a[j]);
+            }
+        }
+        // the slot is rewritten in the next step only after every lane read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (upd) a[k] = l;
         if (piv == T(0) && info == 0) info = k + 1;
         // 4. positions: the pivot row takes position k, the row there moves

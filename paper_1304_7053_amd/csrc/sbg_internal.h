@@ -70,6 +70,8 @@ struct Tuning {
     int unroll;        // tiles per wave step of the direct kernel (a power of two, capped per class)
     int grid;          // work-groups of a persistent grid (rounded up to a multiple of 8)
     int table;         // 1: use the tuned table when one is loaded
+    int blocked;       // sizes above 16 (real types): 0 automatic (the LDS-staged kernel where it measured
+                       // faster), 1 the register kernel only, 2 the LDS-staged kernel wherever it applies
 };
 const Tuning& tuning();
 Tuning& tuning_mut();

@@ -156,7 +156,7 @@ def test_tuning_knobs_round_trip():
     values are rejected without changing anything."""
     lib = sbg.load()
     defaults = {"wg_per_cu": 0, "xcd_chunk": 0, "staged": 2, "tile_bytes": 2048, "tile_bytes16": 8192,
-                "pipeline": 0, "path": 0, "unroll": 0, "grid": 0, "table": 1}
+                "pipeline": 0, "path": 0, "unroll": 0, "grid": 0, "table": 1, "blocked": 0}
     for key, want in defaults.items():
         if "SBG_" + key.upper() not in os.environ:
             assert sbg.get_tuning(key) == want, key
@@ -165,7 +165,7 @@ def test_tuning_knobs_round_trip():
     assert sbg.set_tuning("staged", old) == 1
     for key, bad in (("staged", 3), ("staged", -1), ("wg_per_cu", -1), ("wg_per_cu", 33), ("tile_bytes", 255),
                      ("tile_bytes16", 1 << 21), ("xcd_chunk", -1), ("path", 4), ("unroll", 9), ("grid", -1),
-                     ("table", 2)):
+                     ("table", 2), ("blocked", 3)):
         before = sbg.get_tuning(key)
         assert lib.sbg_set_tuning(key.encode(), bad) == -1
         assert sbg.get_tuning(key) == before

@@ -29,9 +29,97 @@ def _kernel(t, m, n, k, ta="N", tb="N"):
 
 def test_blocked_kernel_selected(gpu_lib):
     for t in "sdcz":
-        assert "gemm_blocked_kernel" in _kernel(t, 17, 4, 4)
-        assert "gemm_blocked_kernel" in _kernel(t, 4, 4, 100)
-        assert "gemm_blocked_kernel" not in _kernel(t, 16, 16, 16)
+        assert "gemm_blocked_kernel" in _kernel(t, 17, 4, 4)      # one block-column: nothing to share
+        assert "gemm_blocked_kernel" in _kernel(t, 4, 4, 100)     # k above 64
+        assert "gemm_blocked" not in _kernel(t, 16, 16, 16)
+    for t in "sd":
+        # the built-in rule: A and B reused, op(A) k-contiguous from 32 on, otherwise from 48 (s) / 64 (d)
+        assert "gemm_blocked_lds_kernel" in _kernel(t, 64, 64, 64)
+        assert "gemm_blocked_lds_kernel" in _kernel(t, 32, 48, 24, "T", "T")
+        assert "gemm_blocked_kernel" in _kernel(t, 24, 24, 24)
+        assert "gemm_blocked_kernel" in _kernel(t, 64, 16, 64)
+        assert ("gemm_blocked_lds_kernel" in _kernel(t, 48, 48, 48)) == (t == "s")
+        with sbg.tuned(blocked=1):
+            assert "gemm_blocked_kernel" in _kernel(t, 64, 64, 64)
+        with sbg.tuned(blocked=2):
+            assert "gemm_blocked_lds_kernel" in _kernel(t, 24, 24, 24)
+            assert "gemm_blocked_lds_kernel" in _kernel(t, 20, 4, 8)
+            assert "gemm_blocked_kernel" in _kernel(t, 17, 4, 4)  # lda * s not a multiple of 16
+    for t in "cz":
+        assert "gemm_blocked_kernel" in _kernel(t, 64, 64, 64)
+
+
+# shapes the LDS-staged kernel takes for every op pair (every size a multiple
+# of 4, so every stored leading dimension is a whole number of 16 bytes)
+LDS_SHAPES = [(20, 20, 20), (32, 32, 32), (36, 44, 28), (64, 48, 40), (24, 64, 60), (4, 40, 12), (64, 64, 64),
+              (52, 8, 64), (16, 16, 20)]
+
+
+@pytest.mark.parametrize("dtype", P.REAL, ids=lambda d: np.dtype(d).name)
+def test_blocked_lds_matches_register_kernel_bitwise(gpu_lib, dtype):
+    """The LDS-staged kernel feeds the same chunks to the same MFMA steps in
+    the same order as the register kernel: results equal bit for bit, for
+    every op pair, ragged blocks, a C leading dimension of its own and
+    matrices at every 16-byte offset (odd batch strides)."""
+    al, be = P.scalars(dtype)
+    g = inputs.rng(408)
+    for ops in P.op_pairs(dtype):
+        for (m, n, k) in LDS_SHAPES:
+            for pad in (0, 1, 3):
+                c = Case(dtype, ops[0], ops[1], m, n, k, 17, al, be, g, ldc=m + 1, pad_stride=pad)
+                say(f"blocked lds {np.dtype(dtype).name} {ops} {m}x{n}x{k} pad={pad}")
+                with sbg.tuned(blocked=2):
+                    assert "gemm_blocked_lds_kernel" in c.describe(), (ops, m, n, k)
+                    out = c.run_gpu()
+                with sbg.tuned(blocked=1):
+                    assert "gemm_blocked_kernel" in c.describe()
+                    ref = c.run_gpu()
+                assert np.array_equal(out.view(np.uint8), ref.view(np.uint8)), (ops, m, n, k, pad)
+                check(c, out, label="blocked lds")
+
+
+@pytest.fixture
+def lds_forced():
+    with sbg.tuned(blocked=2):
+        yield
+
+
+@pytest.mark.parametrize("dtype", P.REAL, ids=lambda d: np.dtype(d).name)
+def test_blocked_lds_special_cases_and_pointer_form(gpu_lib, dtype, lds_forced):
+    g = inputs.rng(409)
+    m, n, k = 36, 20, 44
+    # alpha = 0: A and B (NaN) never read, C = beta C exactly
+    c = Case(dtype, "T", "N", m, n, k, 9, 0.0, -0.75, g)
+    assert "gemm_blocked_lds_kernel" in c.describe()
+    out = c.run_gpu(A=np.full_like(c.A, np.nan), B=np.full_like(c.B, np.nan))
+    assert np.array_equal(c.unpack(out), (np.asarray(c.beta, dtype=dtype) * c.unpack(c.C)).astype(dtype))
+    # beta = 0: C (NaN) never read
+    c2 = Case(dtype, "N", "T", m, n, k, 9, 1.25, 0.0, g)
+    out2 = c2.run_gpu(C=np.full_like(c2.C, np.nan))
+    assert np.all(np.isfinite(c2.unpack(out2)))
+    check(c2, out2, label="blocked lds beta0")
+    # padded layout: gaps keep their bytes
+    c3 = Case(dtype, "N", "N", m, n, k, 11, 1.5, -0.5, g, lda=m + 8, ldb=k + 4, ldc=m + 3, pad_stride=2)
+    assert "gemm_blocked_lds_kernel" in c3.describe()
+    out3 = c3.run_gpu()
+    check(c3, out3, label="blocked lds padded")
+    inside = np.zeros(c3.C.shape, dtype=bool)
+    p = np.arange(c3.batch)[:, None, None]
+    inside[p * c3.sC + np.arange(m)[None, :, None] + np.arange(n)[None, None, :] * c3.ldc] = True
+    assert np.array_equal(out3[~inside].view(np.uint8), c3.C[~inside].view(np.uint8))
+    # pointer arrays in reverse order equal the strided form bit for bit
+    c4 = Case(dtype, "T", "T", m, n, k, 21, 1.5, -0.5, g)
+    ref = c4.run_gpu()
+    dA, dB, dC = to_dev(c4.A), to_dev(c4.B), to_dev(c4.C)
+    order = np.arange(c4.batch)[::-1].copy()
+    esz = dA.element_size()
+    pa = torch.tensor([dA.data_ptr() + int(q) * c4.sA * esz for q in order], dtype=torch.int64, device="cuda")
+    pb = torch.tensor([dB.data_ptr() + int(q) * c4.sB * esz for q in order], dtype=torch.int64, device="cuda")
+    pc = torch.tensor([dC.data_ptr() + int(q) * c4.sC * esz for q in order], dtype=torch.int64, device="cuda")
+    say(f"blocked lds pointer form {np.dtype(dtype).name}")
+    sbg.gemm_batched("T", "T", m, n, k, 1.5, pa, c4.lda, pb, c4.ldb, -0.5, pc, c4.ldc, c4.batch, dC.dtype)
+    torch.cuda.synchronize()
+    assert np.array_equal(from_dev(dC).view(np.uint8), ref.view(np.uint8))
 
 
 @pytest.mark.parametrize("dtype", P.ALL, ids=lambda d: np.dtype(d).name)
@@ -152,15 +240,19 @@ def test_blocked_device_scalar_mode(gpu_lib, dtype):
 
 
 @pytest.mark.parametrize("dtype", P.REAL, ids=lambda d: np.dtype(d).name)
-@pytest.mark.parametrize("s", [24, 32, 64])
-def test_blocked_full_size(gpu_lib, dtype, s):
-    """N = 50,000 (s = 24, 32) or 10,000 (s = 64) square matrices, NN and TN;
-    the first, last and 300 sampled matrices against the oracle."""
+@pytest.mark.parametrize("s", [24, 32, 48, 64])
+@pytest.mark.parametrize("kernel", [2, 1], ids=["lds", "register"])
+def test_blocked_full_size(gpu_lib, dtype, s, kernel):
+    """N = 50,000 (s = 24, 32) or 10,000 (s = 48, 64) square matrices, NN and
+    TN, through the LDS-staged and the register kernel; the first, last and
+    300 sampled matrices against the oracle."""
     g = inputs.rng(407)
-    N = 50_000 if s < 64 else 10_000
+    N = 50_000 if s < 48 else 10_000
     c = Case(dtype, "N", "N", s, s, s, N, 1.5, -0.5, g)
     idx = np.unique(np.concatenate([[0, 1, N - 1], g.choice(N, 300, replace=False)]))
-    for ops in ("NN", "TN"):
-        c.ta, c.tb = ops[0], ops[1]
-        say(f"blocked full {np.dtype(dtype).name} n={s} {ops} N={N}")
-        check(c, c.run_gpu(), idx=idx, label="blocked full")
+    with sbg.tuned(blocked=kernel):
+        for ops in ("NN", "TN"):
+            c.ta, c.tb = ops[0], ops[1]
+            assert ("gemm_blocked_lds_kernel" in c.describe()) == (kernel == 2)
+            say(f"blocked full {np.dtype(dtype).name} n={s} {ops} N={N} kernel={kernel}")
+            check(c, c.run_gpu(), idx=idx, label="blocked full")
