@@ -155,9 +155,15 @@ def _leaves(x):
 
 
 def short(k):
-    k = k.strip()
-    k = re.sub(r"^void ", "", k)
-    return re.sub(r"\(.*\)$", "", k)
+    """Kernel name without 'void ' and without its argument list."""
+    k = re.sub(r"^void ", "", k.strip())
+    if k.endswith(")"):
+        depth = 0
+        for i in range(len(k) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(k[i], 0)
+            if depth == 0:
+                return k[:i]
+    return k
 
 
 def occupancy(sq_csv, regex=None):
