@@ -21,6 +21,10 @@
 //    and re-read that matrix's A and B blocks from the same L2.
 #pragma once
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "gemm_direct.h"
 
 namespace sbg {
@@ -139,9 +143,8 @@ __global__ __launch_bounds__(256) void gemm_blocked_kernel(const GemmArgs<T> a)
 //  3. a barrier, then the next matrix overwrites the images.
 // A and B are read from HBM once per matrix.  The host takes this kernel
 // where it measured faster than the register kernel: when both A and B are
-// reused (at least two block-rows and two block-columns) and op(A) is
-// k-contiguous (op T or C) or the largest size reaches 48 (4-byte types) or
-// 64 (8-byte types).
+// reused (at least two block-rows and two block-columns) and the largest size
+// reaches 32, or 48 for 4-byte types whose op(A) is not k-contiguous.
 
 typedef unsigned int blk_u4 __attribute__((ext_vector_type(4)));
 
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(256) void gemm_blocked_lds_kernel(const GemmArgs<T>
     using R = typename Tr<T>::R;
     using acc_t = typename Mfma<R>::acc_t;
     constexpr int S = (int)sizeof(T);
-    constexpr int CH = 8;                           // chunks per thread per copy pass
+    constexpr int CHL = 5;                          // chunks of each operand per thread per copy pass
     using G4 = __attribute__((address_space(1))) const blk_u4*;
     using L4 = __attribute__((address_space(3))) blk_u4*;
     const LaneGeom<16, R> L;
@@ -195,29 +198,52 @@ __global__ __launch_bounds__(256) void gemm_blocked_lds_kernel(const GemmArgs<T>
         const uintptr_t ga = reinterpret_cast<uintptr_t>(Ab), gb = reinterpret_cast<uintptr_t>(Bb);
         const int offA = (int)(ga & 15), offB = (int)(gb & 15);
 
-        // 1. A and B into LDS
+        // 1. A and B into LDS: thread t copies chunks t, t + 256, ... of each
+        // operand's list (chunk i = column i / nq, chunk i % nq of it), A's and
+        // B's in flight together; the (column, chunk) pair advances by the
+        // constant step 256 = dj nq + dq, so no division per chunk
         if (!skipAB) {
             const int nqA = (offA + g.rowsA * S + 15) >> 4, nqB = (offB + g.rowsB * S + 15) >> 4;
-            const int totA = g.colsA * nqA, tot = totA + g.colsB * nqB;
+            const int totA = g.colsA * nqA, totB = g.colsB * nqB;
+            const int tot = totA > totB ? totA : totB;
             const uintptr_t a16 = ga & ~(uintptr_t)15, b16 = gb & ~(uintptr_t)15;
-            for (int base = 0; base < tot; base += 256 * CH) {
-                blk_u4 r[CH];
-                int dst[CH];
+            const int tid = (int)threadIdx.x;
+            int jA = tid / nqA, qA = tid - jA * nqA;
+            int jB = tid / nqB, qB = tid - jB * nqB;
+            const int djA = 256 / nqA, dqA = 256 - djA * nqA;
+            const int djB = 256 / nqB, dqB = 256 - djB * nqB;
+            for (int base = 0; base < tot; base += 256 * CHL) {
+                blk_u4 ra[CHL], rb[CHL];
+                int da[CHL], db[CHL];
 #pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const int idx = base + (int)threadIdx.x + 256 * c;
-                    const bool inA = idx < totA;
-                    const int li = inA ? idx : idx - totA;
-                    const int nq = inA ? nqA : nqB;
-                    const int j = li / nq, q = li - j * nq;
-                    // past the list: chunk 0 of A (holds A's first element)
-                    const uintptr_t src = idx >= tot ? a16 : (inA ? a16 + j * ldab : b16 + j * ldbb) + 16 * q;
-                    dst[c] = idx >= tot ? -1 : (inA ? j * g.pitchA : g.offB + j * g.pitchB) + 16 * q;
-                    r[c] = *(G4)src;
+                for (int c = 0; c < CHL; ++c) {
+                    const int idx = base + tid + 256 * c;
+                    const bool okA = idx < totA, okB = idx < totB;
+                    // a slot past its list reads chunk 0 of its operand (holds its first element)
+                    const uintptr_t sa = okA ? a16 + jA * ldab + 16 * qA : a16;
+                    const uintptr_t sb = okB ? b16 + jB * ldbb + 16 * qB : b16;
+                    da[c] = okA ? jA * g.pitchA + 16 * qA : -1;
+                    db[c] = okB ? g.offB + jB * g.pitchB + 16 * qB : -1;
+                    ra[c] = *(G4)sa;
+                    rb[c] = *(G4)sb;
+                    qA += dqA;
+                    jA += djA;
+                    if (qA >= nqA) {
+                        qA -= nqA;
+                        ++jA;
+                    }
+                    qB += dqB;
+                    jB += djB;
+                    if (qB >= nqB) {
+                        qB -= nqB;
+                        ++jB;
+                    }
                 }
 #pragma unroll
-                for (int c = 0; c < CH; ++c)
-                    if (dst[c] >= 0) *(L4)(blk_smem + dst[c]) = r[c];
+                for (int c = 0; c < CHL; ++c) {
+                    if (da[c] >= 0) *(L4)(blk_smem + da[c]) = ra[c];
+                    if (db[c] >= 0) *(L4)(blk_smem + db[c]) = rb[c];
+                }
             }
         }
         __syncthreads();
@@ -292,8 +318,8 @@ constexpr int kBlkLdsMax = 96 * 1024;
 // complex types, a size above 64, k = 0, a leading dimension of A or B
 // whose byte size is not a multiple of 16, images above kBlkLdsMax, or a
 // shape where it measured slower than the register kernel (A or B not
-// reused across blocks; op(A) with m contiguous below size 48 for 4-byte
-// types and 64 for 8-byte types).
+// reused across blocks; sizes below 32; 4-byte types with op(A) N or R
+// below 48).
 template <typename T>
 inline int blocked_lds_plan(const GemmArgs<T>& a, BlkLds& g)
 {
@@ -307,7 +333,7 @@ inline int blocked_lds_plan(const GemmArgs<T>& a, BlkLds& g)
         if (tuning().blocked != 2) {
             const int mx = a.m > a.n ? (a.m > a.k ? a.m : a.k) : (a.n > a.k ? a.n : a.k);
             if (a.m <= 16 || a.n <= 16) return 0;
-            if (!a.a_trans && mx < (S == 4 ? 48 : 64)) return 0;
+            if (!a.a_trans && mx < (S == 4 ? 48 : 32)) return 0;
             if (a.a_trans && mx < 32) return 0;
         }
         g.rowsA = a.a_trans ? a.k : a.m;
@@ -330,9 +356,19 @@ hipError_t launch_blocked_lds_u(GemmArgs<T> a, const BlkLds& g, int bytes, hipSt
                    : (bn ? gemm_blocked_lds_kernel<T, U, false, true, PTR>
                          : gemm_blocked_lds_kernel<T, U, false, false, PTR>);
     if (bytes > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        if (e != hipSuccess) return e;
+        // raised once per kernel and device to the largest image size any call needs
+        static std::mutex mu;
+        static std::map<std::pair<const void*, int>, bool> raised;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+        std::lock_guard<std::mutex> lock(mu);
+        bool& done = raised[{reinterpret_cast<const void*>(kern), dev}];
+        if (!done) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBlkLdsMax);
+            if (e != hipSuccess) return e;
+            done = true;
+        }
     }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, bytes) != hipSuccess || per_cu < 1)

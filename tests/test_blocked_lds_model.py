@@ -17,7 +17,7 @@ import itertools
 import numpy as np
 
 MAX_BYTES = 96 * 1024
-THREADS, CH = 256, 8
+THREADS, CH = 256, 6
 
 
 def pitch(rows, s):
@@ -37,7 +37,7 @@ def plan(m, n, k, lda, ldb, at, bt, s, forced=True):
         mx = max(m, n, k)
         if m <= 16 or n <= 16:
             return None
-        if not at and mx < (48 if s == 4 else 64):
+        if not at and mx < (48 if s == 4 else 32):
             return None
         if at and mx < 32:
             return None
@@ -62,32 +62,42 @@ def check(m, n, k, at, bt, s, padA, padB, offA, offB_g):
     a16, b16 = ga & ~15, gb & ~15
     nqA = ((ga & 15) + rA * s + 15) >> 4
     nqB = ((gb & 15) + rB * s + 15) >> 4
-    totA = cA * nqA
-    tot = totA + cB * nqB
-    passes = -(-tot // (THREADS * CH))
-    idx = np.arange(passes * THREADS * CH, dtype=np.int64)
-    inA = idx < totA
-    li = np.where(inA, idx, idx - totA)
-    nq = np.where(inA, nqA, nqB)
-    j = li // nq
-    q = li - j * nq
-    past = idx >= tot
-    src = np.where(past, a16, np.where(inA, a16 + j * lda * s, b16 + j * ldb * s) + 16 * q)
-    dst = np.where(past, -1, np.where(inA, j * pA, offB + j * pB) + 16 * q)
-    assert np.all(src % 16 == 0)
-    # each chunk overlaps its column's bytes (a past-the-list chunk: A's column 0)
-    col_lo = np.where(past | inA, ga + np.where(past, 0, j) * lda * s, gb + j * ldb * s)
-    col_hi = col_lo + np.where(past | inA, rA, rB) * s
-    assert np.all(src < col_hi) and np.all(src + 16 > col_lo), (m, n, k, at, bt, s)
-    # LDS writes: inside the column's region and the allocation, each once
-    w = dst >= 0
-    reg_lo = np.where(inA, j * pA, offB + j * pB)
-    reg_hi = reg_lo + np.where(inA, pA, pB)
-    assert np.all(dst[w] >= reg_lo[w]) and np.all(dst[w] + 16 <= reg_hi[w]), (m, n, k, s)
-    assert np.all(dst[w] + 16 <= total)
-    assert len(np.unique(dst[w])) == int(w.sum())
+    totA, totB = cA * nqA, cB * nqB
+    passes = -(-max(totA, totB) // (THREADS * CH))
+    # the kernel's per-thread walk: (column, chunk) starts at divmod(t, nq) and
+    # advances by the constant step 256 = dj nq + dq with one carry
+    srcs, dsts = [], []
+    for name, tot, nq, o16, ld, img, pit, base in (("A", totA, nqA, a16, lda * s, 0, pA, ga),
+                                                   ("B", totB, nqB, b16, ldb * s, offB, pB, gb)):
+        t = np.arange(THREADS)
+        j, q = t // nq, t % nq
+        dj, dq = THREADS // nq, THREADS % nq
+        for c in range(passes * CH):
+            idx = c * THREADS + t           # slot c of every thread, in pass order
+            assert np.array_equal(j * nq + q, idx)
+            ok = idx < tot
+            src = np.where(ok, o16 + j * ld + 16 * q, o16)
+            dst = np.where(ok, img + j * pit + 16 * q, -1)
+            lo = np.where(ok, base + j * ld, base)
+            hi = lo + np.where(ok, (rA if name == "A" else rB) * s, s)
+            assert np.all(src % 16 == 0)
+            assert np.all(src < hi) and np.all(src + 16 > lo), (name, m, n, k, at, bt, s)
+            w = ok
+            assert np.all(dst[w] >= img + j[w] * pit) and np.all(dst[w] + 16 <= img + (j[w] + 1) * pit)
+            srcs.append(src[w])
+            dsts.append(dst[w])
+            q = q + dq
+            j = j + dj
+            carry = q >= nq
+            q = np.where(carry, q - nq, q)
+            j = np.where(carry, j + 1, j)
+    src = np.concatenate(srcs)
+    dst = np.concatenate(dsts)
+    assert len(dst) == totA + totB                 # every chunk of both lists, once
+    assert np.all(dst + 16 <= total)
+    assert len(np.unique(dst)) == len(dst)
     # element (i, j) of each image: its LDS bytes come from its global bytes
-    lds_src = dict(zip(dst[w].tolist(), src[w].tolist()))
+    lds_src = dict(zip(dst.tolist(), src.tolist()))
     for (rows, cols, base, ld, img0, pit) in ((rA, cA, ga, lda, 0, pA), (rB, cB, gb, ldb, offB, pB)):
         for jj in sorted({0, cols // 2, cols - 1}):
             for ii in sorted({0, rows // 2, rows - 1}):
@@ -125,10 +135,11 @@ def test_plan_rejects_what_the_kernel_cannot_take():
     assert plan(21, 20, 20, 21, 20, False, False, 4) is None          # lda * 4 not a multiple of 16
     assert plan(64, 64, 64, 64, 64, False, False, 8) is not None      # f64 n = 64: 2 x 64 x 528 bytes
     assert plan(64, 64, 64, 64 * 3, 64, False, False, 8) is not None  # padding does not change the image
-    # the automatic choice: reuse of A and B, k-contiguous op(A) from 32, else 48 (4 bytes) / 64 (8 bytes)
+    # the automatic choice: reuse of A and B from size 32 on; 4-byte types with op(A) N from 48
     assert plan(24, 24, 24, 24, 24, False, False, 4, forced=False) is None
     assert plan(32, 32, 32, 32, 32, True, False, 4, forced=False) is not None
+    assert plan(32, 32, 32, 32, 32, False, False, 4, forced=False) is None
+    assert plan(32, 32, 32, 32, 32, False, False, 8, forced=False) is not None
     assert plan(48, 48, 48, 48, 48, False, False, 4, forced=False) is not None
-    assert plan(48, 48, 48, 48, 48, False, False, 8, forced=False) is None
     assert plan(64, 16, 64, 64, 64, False, False, 4, forced=False) is None
     assert pitch(64, 4) == 272 and pitch(64, 8) == 528 and pitch(32, 4) == 144

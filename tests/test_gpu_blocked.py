@@ -33,12 +33,13 @@ def test_blocked_kernel_selected(gpu_lib):
         assert "gemm_blocked_kernel" in _kernel(t, 4, 4, 100)     # k above 64
         assert "gemm_blocked" not in _kernel(t, 16, 16, 16)
     for t in "sd":
-        # the built-in rule: A and B reused, op(A) k-contiguous from 32 on, otherwise from 48 (s) / 64 (d)
+        # the built-in rule: A and B reused, from size 32 on, for s with op(A) N from 48
         assert "gemm_blocked_lds_kernel" in _kernel(t, 64, 64, 64)
+        assert "gemm_blocked_lds_kernel" in _kernel(t, 48, 48, 48)
         assert "gemm_blocked_lds_kernel" in _kernel(t, 32, 48, 24, "T", "T")
         assert "gemm_blocked_kernel" in _kernel(t, 24, 24, 24)
         assert "gemm_blocked_kernel" in _kernel(t, 64, 16, 64)
-        assert ("gemm_blocked_lds_kernel" in _kernel(t, 48, 48, 48)) == (t == "s")
+        assert ("gemm_blocked_lds_kernel" in _kernel(t, 32, 32, 32)) == (t == "d")
         with sbg.tuned(blocked=1):
             assert "gemm_blocked_kernel" in _kernel(t, 64, 64, 64)
         with sbg.tuned(blocked=2):
