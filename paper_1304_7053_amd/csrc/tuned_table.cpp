@@ -24,6 +24,7 @@ namespace sbg {
 namespace {
 
 constexpr int kVersion = 1;
+constexpr int kMaxDepth = 64;
 
 struct Table {
     bool loaded = false;
@@ -78,9 +79,18 @@ public:
         i_ += (size_t)(e - b);
         return v;
     }
-    // skip any value
-    void skip()
+    // an integer field: 0 unless the number is finite and fits an int (a
+    // double outside int's range must not be converted)
+    int integer()
     {
+        const double v = num();
+        return (v >= -2147483648.0 && v <= 2147483647.0) ? (int)v : 0;
+    }
+    // skip any value (nesting deeper than kMaxDepth fails the read instead of
+    // recursing without bound)
+    void skip(int depth = 0)
+    {
+        if (depth > kMaxDepth) return fail();
         const char c = peek();
         if (c == '"') {
             str();
@@ -90,13 +100,13 @@ public:
             do {
                 str();
                 if (!eat(':')) return fail();
-                skip();
+                skip(depth + 1);
             } while (ok_ && eat(','));
             if (!eat('}')) fail();
         } else if (c == '[') {
             eat('[');
             if (eat(']')) return;
-            do skip();
+            do skip(depth + 1);
             while (ok_ && eat(','));
             if (!eat(']')) fail();
         } else if (c == 't' || c == 'f' || c == 'n') {
@@ -138,11 +148,11 @@ void read_entry(Reader& r, Table& t)
                 else if (key == "ops") ops = v;
                 else if (key == "path") path = v;
             } else if (r.peek() == '-' || std::isdigit((unsigned char)r.peek())) {
-                const double v = r.num();
-                if (key == "size") size = (int)v;
-                else if (key == "unroll") unroll = (int)v;
-                else if (key == "wg_per_cu") wg = (int)v;
-                else if (key == "xcd_chunk") xcd = (int)v;
+                const int v = r.integer();
+                if (key == "size") size = v;
+                else if (key == "unroll") unroll = v;
+                else if (key == "wg_per_cu") wg = v;
+                else if (key == "xcd_chunk") xcd = v;
             } else {
                 r.skip();
             }
@@ -175,7 +185,7 @@ void parse(const std::string& text, Table& t)
             const std::string key = r.str();
             if (!r.eat(':')) return;
             if (key == "version") {
-                version = (int)r.num();
+                version = r.integer();
             } else if (key == "entries") {
                 if (!r.eat('[')) return;
                 if (!r.eat(']')) {
