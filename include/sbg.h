@@ -322,7 +322,9 @@ int sbg_version(void);
  * Knobs are process-wide, for tuning sweeps and A/B comparisons (not
  * thread-safe against concurrent calls; set them before launching).  Keys
  * (0 = automatic unless stated):
- *   "wg_per_cu"   persistent grids: work-groups per CU, 0..32 (automatic: 4);
+ *   "wg_per_cu"   persistent grids: work-groups per CU, 0..32 (automatic: 4,
+ *                 capped by the kernel's residency; a set value is taken as
+ *                 given and may exceed it);
  *   "xcd_chunk"   consecutive work units per XCD run, >= 0 (automatic: 16);
  *   "staged"      packed strided batches through the LDS-staged kernel:
  *                 0 never, 1 always, 2 automatic (default);

@@ -153,17 +153,21 @@ inline int resident_per_cu(K kernel)
     return resident_blocks_per_cu(reinterpret_cast<const void*>(kernel));
 }
 
-// Persistent grid for `units` independent wave-sized work units: at most the
-// resident work-groups (capped by the tuning knob), a multiple of 8 so the
-// XCD renumbering is exact; sets the XCD run length to a divisor of the
-// waves per XCD.
+// Persistent grid for `units` independent wave-sized work units, a multiple
+// of 8 so the XCD renumbering is exact: by default 4 work-groups per CU
+// capped by the kernel's residency; an explicit choice (tuned table entry or
+// knob) is taken as given, so it may also ask for more work-groups than can
+// be resident at once (they start as earlier ones finish, which evens out
+// the end of the launch).  Sets the XCD run length to a divisor of the waves
+// per XCD.
 template <typename T, typename K>
 inline int64_t persistent_grid(K kernel, int64_t units, GemmArgs<T>& a)
 {
     const Tuning& tu = tuning();
     int per_cu = resident_per_cu(kernel);
     const int want = a.plan_wg > 0 ? a.plan_wg : (tu.wg_per_cu > 0 ? tu.wg_per_cu : 4);
-    if (per_cu > want) per_cu = want;
+    if (a.plan_wg > 0 || tu.wg_per_cu > 0) per_cu = want;
+    else if (per_cu > want) per_cu = want;
     const int64_t wg_needed = (units + 3) / 4;
     const int64_t cap = tu.grid > 0 ? (int64_t)tu.grid : (int64_t)device_cu_count() * per_cu;
     int64_t grid = wg_needed < cap ? wg_needed : cap;

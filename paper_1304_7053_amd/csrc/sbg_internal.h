@@ -59,7 +59,7 @@ struct GemmArgs {
 // sbg_set_tuning or the SBG_* environment variables (read once per process),
 // override the table -- for tuning sweeps and A/B comparisons.
 struct Tuning {
-    int wg_per_cu;     // persistent grids: work-groups per CU (capped by occupancy)
+    int wg_per_cu;     // persistent grids: work-groups per CU (0: 4, capped by occupancy; set: as given)
     int xcd_chunk;     // consecutive work units per XCD run
     int staged;        // 0 never, 1 every packed strided batch, 2 automatic
     int tile_bytes;    // per-wave bytes in flight per step, size classes 4 and 8

@@ -132,7 +132,7 @@ def tune_key(w, ops, form, reps):
                     us, entry["unroll"] = t, u
             if entry["unroll"]:
                 kn["unroll"] = entry["unroll"]
-        for wg in (1, 2, 3, 6, 8):
+        for wg in (1, 2, 3, 6, 8, 16, 32):
             t = measure(w, ops, form, dict(kn, wg_per_cu=wg), reps)
             if t < us:
                 us, entry["wg_per_cu"] = t, wg

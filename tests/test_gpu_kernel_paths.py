@@ -2,8 +2,9 @@
 one: the team kernel for sizes <= 8 wherever it applies, the MFMA tile
 kernels for those sizes (with the LDS-staged kernel for packed strided
 batches, the prefetching (pipelined) direct kernel, the extreme tile unrolls
--- one tile per group, and the largest unroll the size class allows -- and a
-persistent grid of one work-group per CU walking many work units).  Each path reruns the parity cases
+-- one tile per group, and the largest unroll the size class allows -- a
+persistent grid of one work-group per CU walking many work units, and one of
+32 work-groups per CU, more than can be resident).  Each path reruns the parity cases
 of the default path (same oracle, same 4 max(k,1) u acceptance test), and the
 kernel name the library reports confirms which kernel ran."""
 import numpy as np
@@ -22,6 +23,7 @@ PATHS = {
     "unroll1": dict(staged=0, pipeline=0, tile_bytes=256, tile_bytes16=256, path=1),
     "unrollmax": dict(staged=0, pipeline=0, tile_bytes=1 << 20, tile_bytes16=1 << 20, path=1),
     "onewg": dict(staged=0, pipeline=0, wg_per_cu=1, xcd_chunk=1, path=1),
+    "oversub": dict(staged=0, pipeline=0, wg_per_cu=32, path=1),
 }
 
 
@@ -52,7 +54,7 @@ def test_path_parity(gpu_lib, path, dtype):
         P.test_device_scalar_mode(gpu_lib, dtype)
 
 
-@pytest.mark.parametrize("path", ["team", "staged", "pipelined"])
+@pytest.mark.parametrize("path", ["team", "staged", "pipelined", "oversub"])
 @pytest.mark.parametrize("dtype", P.REAL, ids=lambda d: np.dtype(d).name)
 def test_path_full_size(gpu_lib, path, dtype):
     """The N = 100,000 size sweep through the alternative paths."""
