@@ -151,30 +151,63 @@ __global__ __launch_bounds__(256) void quant_e4m3_kernel(const QuantArgs q)
         }
         amax = row16_max(amax);
         const float s = amax > 0.f ? amax / 448.0f : 1.0f;
-        float qv[16];
-        bool wide = false;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            qv[e] = v[e] / s;
-            wide = wide || !(fabsf(qv[e]) < 464.0f);   // NaN too
-        }
-        // The hardware conversion (round to nearest even) gives the same codes
-        // as enc_e4m3 for every binary32 value of magnitude below 464 (checked
-        // exhaustively on the device); quotients of finite inputs never
-        // exceed 448 (1 + 2^-23).  A wave holding a larger value or a NaN
-        // (non-finite inputs) takes the software encoder.
+        // Fast path: multiply by the hardware reciprocal of s (1 ulp) instead
+        // of dividing.  The product is within 2^-22 relative of the exact
+        // quotient v / s and of its rounded value fl(v / s), so fl(v / s) lies
+        // in [lo, hi] = qa -+ |qa| 2^-20.  The conversion rounds monotonically,
+        // so when lo and hi give the same code every value between them does,
+        // fl(v / s) included: that code is the exact one.  A wave with an
+        // element whose bracket straddles a rounding boundary (about one
+        // element in 65,000 for values spread over the e4m3 range), a scale
+        // outside [2^-100, 2^100] or a non-finite value divides instead.  The hardware conversion gives the codes of
+        // enc_e4m3 for every binary32 value of magnitude below 464 (checked
+        // exhaustively on the device); here every converted value is below
+        // 460.
         unsigned codes[4];
-        if (__builtin_amdgcn_ballot_w64(wide) == 0) {
+        bool slow = !(s >= 0x1p-100f && s <= 0x1p100f);   // NaN too
+        {
+            const float r = __builtin_amdgcn_rcpf(s);
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
-                const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d], qv[4 * d + 1], 0, false);
-                codes[d] = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d + 2], qv[4 * d + 3], lo, true);
-            }
-        } else {
+                float lo[4], hi[4];
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
-                codes[d] = (unsigned)enc_e4m3(qv[4 * d]) | ((unsigned)enc_e4m3(qv[4 * d + 1]) << 8) |
-                           ((unsigned)enc_e4m3(qv[4 * d + 2]) << 16) | ((unsigned)enc_e4m3(qv[4 * d + 3]) << 24);
+                for (int j = 0; j < 4; ++j) {
+                    const float qa = v[4 * d + j] * r;
+                    slow = slow || !(fabsf(qa) < 460.0f);
+                    lo[j] = __builtin_fmaf(-fabsf(qa), 0x1p-20f, qa);
+                    hi[j] = __builtin_fmaf(fabsf(qa), 0x1p-20f, qa);
+                }
+                const int l0 = __builtin_amdgcn_cvt_pk_fp8_f32(lo[0], lo[1], 0, false);
+                const int l1 = __builtin_amdgcn_cvt_pk_fp8_f32(lo[2], lo[3], l0, true);
+                const int h0 = __builtin_amdgcn_cvt_pk_fp8_f32(hi[0], hi[1], 0, false);
+                const int h1 = __builtin_amdgcn_cvt_pk_fp8_f32(hi[2], hi[3], h0, true);
+                slow = slow || l1 != h1;
+                codes[d] = (unsigned)l1;
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(slow) != 0) {
+            float qv[16];
+            bool wide = false;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                qv[e] = v[e] / s;
+                wide = wide || !(fabsf(qv[e]) < 464.0f);   // NaN too
+            }
+            // quotients of finite inputs never exceed 448 (1 + 2^-23); a wave
+            // holding a larger value or a NaN takes the software encoder
+            if (__builtin_amdgcn_ballot_w64(wide) == 0) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d], qv[4 * d + 1], 0, false);
+                    codes[d] = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(qv[4 * d + 2], qv[4 * d + 3], lo, true);
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    codes[d] = (unsigned)enc_e4m3(qv[4 * d]) | ((unsigned)enc_e4m3(qv[4 * d + 1]) << 8) |
+                               ((unsigned)enc_e4m3(qv[4 * d + 2]) << 16) |
+                               ((unsigned)enc_e4m3(qv[4 * d + 3]) << 24);
+            }
         }
         if (mine) {
             unsigned char* qc = Q + (int64_t)t * ldq;

@@ -146,6 +146,47 @@ def test_quantiser_vbatched_matches_oracle_bitwise(gpu_lib, dist):
     assert np.all(Qg[mask] == 0xAB)
 
 
+def test_quantiser_rounding_boundaries_full_size(gpu_lib):
+    """200,000 16 x 16 matrices (the var-size workload's count at its largest
+    size), codes and scales bit for bit against the oracle.  The first 3,072
+    are built so that v / s falls near every e4m3 rounding boundary with
+    scales 1, 3, 5, 0.75, 7 2^-20 and 3 2^40, alternating by wave: on it or up
+    to 3 ulps away (ties included; the reciprocal product's bracket straddles
+    the boundary and the wave divides), or 20 and 40 ulps away (the wave keeps
+    the product's codes).  The rest are normal values, mostly on the
+    reciprocal path."""
+    g = inputs.rng(4, salt=14)
+    batch, n = 200_000, 16
+    X = g.standard_normal(batch * n * n).astype(np.float32)
+    codes = np.arange(0x7F)
+    vals = np.unique([oracle.decode(int(c), "e4m3") for c in codes])
+    mids = (vals[1:] + vals[:-1]) / 2
+    scs = np.array([1.0, 3.0, 5.0, 0.75, 7.0 * 2.0 ** -20, 3.0 * 2.0 ** 40], dtype=np.float32)
+    K = 3072
+    NEAR, FAR = np.arange(-3, 4), np.array([-40, -20, 20, 40])
+    for p in range(K):
+        sc = scs[p % len(scs)]
+        el = np.arange(n * n - 1) + p
+        v = (np.where(el % 2, -1.0, 1.0) * mids[(el // 2) % len(mids)] * np.float64(sc)).astype(np.float32)
+        ulps = NEAR if (p // 4) % 2 == 0 else FAR             # 4 matrices to a wave: whole waves near or far
+        k = ulps[(el // (2 * len(mids)) + p) % len(ulps)]   # ulps of magnitude away from the boundary
+        v = (v.view(np.int32) + k.astype(np.int32)).view(np.float32)
+        X[p * n * n] = np.float32(448.0) * sc
+        X[p * n * n + 1:(p + 1) * n * n] = v
+    dX = to_dev(X)
+    dQ = torch.full((batch * n * n,), 0xAB, dtype=torch.uint8, device="cuda")
+    dS = torch.zeros(batch, dtype=torch.float32, device="cuda")
+    say(f"quantise {batch} x {n}x{n}, rounding boundaries in the first {K}")
+    sbg.quantize_e4m3_strided(n, n, dX, n, n * n, dQ, n, n * n, dS, batch)
+    torch.cuda.synchronize()
+    Q, offQ, S = oracle.quant_e4m3(X, np.arange(batch, dtype=np.int64) * n * n, n, n, n, batch)
+    assert np.array_equal(S[:K], np.resize(scs, K))       # the built matrices have the scales they were built for
+    Sg, Qg = from_dev(dS), from_dev(dQ)
+    assert np.array_equal(Sg, S)
+    bad = np.nonzero(Qg != Q[: batch * n * n])[0]
+    assert bad.size == 0, (bad.size, bad[:8], X[bad[:8]])
+
+
 @pytest.mark.parametrize("dist", ["uniform", "logu"])
 def test_fp8_scaled_strided(gpu_lib, dist):
     g = inputs.rng(4, salt=12)
