@@ -210,10 +210,29 @@ __global__ __launch_bounds__(256) void quant_e4m3_kernel(const QuantArgs q)
             }
         }
         if (mine) {
-            unsigned char* qc = Q + (int64_t)t * ldq;
+            // The column's rows bytes as up to 3 head bytes (to the first
+            // 4-byte boundary), whole aligned dwords, and up to 3 tail bytes:
+            // at most 10 stores in place of 16 byte stores, every one inside
+            // [qc, qc + rows).
+            const GByw qc = (GByw)(Q + (int64_t)t * ldq);
+            const int h0 = (int)((0u - (unsigned)reinterpret_cast<uintptr_t>(qc)) & 3u);
+            const int h = h0 < rows ? h0 : rows;
+            const int nd = (rows - h) >> 2;
+            const int tb = h + 4 * nd;
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if (e < rows) qc[e] = (unsigned char)(codes[e >> 2] >> (8 * (e & 3)));
+            for (int j = 0; j < 3; ++j)
+                if (j < h) qc[j] = (unsigned char)(codes[0] >> (8 * j));
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < nd)
+                    *(__attribute__((address_space(1))) unsigned*)(qc + h + 4 * i) =
+                        __builtin_amdgcn_alignbyte(i < 3 ? codes[i + 1] : 0u, codes[i], (unsigned)h);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int e = tb + j;
+                const unsigned w = e < 4 ? codes[0] : (e < 8 ? codes[1] : (e < 12 ? codes[2] : codes[3]));
+                if (e < rows) qc[e] = (unsigned char)(w >> (8 * (e & 3)));
+            }
         }
         if (ok && t == 0) q.scales[p] = s;   // an empty matrix gets scale 1
     }
